@@ -99,6 +99,7 @@ def lib():
         L.gro_dephase.argtypes = [vp, C.c_int64, C.POINTER(_Dephase)]
         L.gro_parallel_step.argtypes = [vp, C.c_int64, C.POINTER(_Exit)]
         L.gro_advance.argtypes = [vp, C.c_int64, C.POINTER(C.c_int64)]
+        L.gro_step_replicas.argtypes = [vp, C.c_int64, C.c_int32, C.c_int32]
         L.gro_simulated_time.argtypes = [vp]
         L.gro_simulated_time.restype = C.c_double
         for f in ("gro_simulated_steps", "gro_global_step"):
@@ -314,6 +315,9 @@ class System:
         o = _Exit()
         rc = _check(lib().gro_parallel_step(self._h, int(max_checks), C.byref(o)), "parallel_step")
         return rc, dict(M=o.M, k=o.k, to_state=o.to_state, tau_steps=o.tau_steps, tau=o.tau)
+
+    def step_replicas(self, nsteps, r_lo, r_hi):
+        _check(lib().gro_step_replicas(self._h, int(nsteps), int(r_lo), int(r_hi)), "step_replicas")
 
     def advance(self, nsteps):
         fec = np.zeros(self.R, np.int64)

@@ -105,6 +105,7 @@ int  gro_decorrelate(gro_sys *S, int64_t t_corr, int64_t max_steps, gro_event *e
 int  gro_dephase(gro_sys *S, int64_t max_steps, gro_dephase_result *o);
 int  gro_parallel_step(gro_sys *S, int64_t max_checks, gro_exit_result *o);
 int  gro_advance(gro_sys *S, int64_t nsteps, int64_t *first_exit_check);
+int  gro_step_replicas(gro_sys *S, int64_t nsteps, int32_t r_lo, int32_t r_hi);
 double  gro_simulated_time(const gro_sys *S);
 int64_t gro_simulated_steps(const gro_sys *S);
 int64_t gro_global_step(const gro_sys *S);

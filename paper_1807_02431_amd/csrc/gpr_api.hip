@@ -1,0 +1,1003 @@
+// gpr_api.hip -- host runtime behind the C ABI of include/gpr.h.
+//
+// Owns the device buffers of a system, drives the stepping paths and the per-check
+// bookkeeping kernels, and keeps the Gen.ParRep phase machine (transient propagation,
+// Fleming-Viot convergence step, parallel step; Sec. 2.4, Fig. 1) on the host: every
+// decision is taken from a small status word read back once per check.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gpr.h"
+#include "gpr_kernels.h"
+
+using namespace gpr;
+
+namespace {
+
+constexpr double COULOMB_F = 138.935458;
+enum { PH_IDLE = 0, PH_DECORR = 1, PH_DEPHASE = 2, PH_CONVERGED = 3, PH_PARALLEL = 4 };
+
+thread_local std::string g_thread_err;
+
+} // namespace
+
+struct gpr_system {
+    Dev d{};
+    std::vector<void *> bufs;
+    hipStream_t stream = nullptr;
+    int path = GPR_PATH_PLAIN;
+    int bt_persist = 0;
+    int n = 0, R = 0, np = 0, kind = 0, nobs = 0;
+    int t_gr = 1, tcd = 1, tcp = 1;
+    double tol = 0, dt = 0, kT = 0;
+    long long t_min = 0;
+    // phase machine
+    long long s = 0, tsim = 0;
+    int omega = -1, phase = PH_IDLE;
+    int dc_from = -1, dc_omega = -1;
+    long long dc_resid = 0, dc_steps = 0;
+    long long dp_t = 0, nsamp = 0, n_branch = 0;
+    long long par_M = 0;
+    // scratch
+    Status *st_dev = nullptr, *st_host = nullptr;
+    double *obs_out = nullptr;
+    int *donor = nullptr, *surv = nullptr;
+    long long *fec = nullptr;
+    size_t lds_persist = 0, lds_nb = 0, lds_stage = 0;
+    int persist_ok = 0;
+    std::string err;
+};
+
+namespace {
+
+gpr_status fail(gpr_system *s, gpr_status code, const std::string &msg)
+{
+    if (s) s->err = msg;
+    g_thread_err = msg;
+    return code;
+}
+
+#define HIPCHK(sys, call)                                                                        \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail((sys), GPR_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define LAUNCHCHK(sys)                                                                           \
+    do {                                                                                         \
+        hipError_t e_ = hipGetLastError();                                                       \
+        if (e_ != hipSuccess)                                                                    \
+            return fail((sys), GPR_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+template <class T>
+hipError_t dalloc(gpr_system *s, T **p, size_t count)
+{
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+    if (e != hipSuccess) return e;
+    s->bufs.push_back(q);
+    *p = (T *)q;
+    return hipMemset(q, 0, std::max<size_t>(count, 1) * sizeof(T));
+}
+
+template <class T>
+hipError_t upload(gpr_system *s, T **p, const std::vector<T> &h)
+{
+    hipError_t e = dalloc(s, p, h.size());
+    if (e != hipSuccess || h.empty()) return e;
+    return hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+bool idx_ok(const int32_t *a, long cnt, int n)
+{
+    if (cnt > 0 && !a) return false;
+    for (long k = 0; k < cnt; ++k) if (a[k] < 0 || a[k] >= n) return false;
+    return true;
+}
+
+// sorts terms of width w by their smallest atom; returns order, start offsets, span
+void sort_terms(const int32_t *atoms, int cnt, int w, int n, std::vector<int> &order, std::vector<int> &start, int &span)
+{
+    order.resize(cnt);
+    std::vector<int> mn(cnt);
+    span = 0;
+    for (int t = 0; t < cnt; ++t) {
+        int lo = atoms[t * w], hi = atoms[t * w];
+        for (int k = 1; k < w; ++k) { lo = std::min(lo, (int)atoms[t * w + k]); hi = std::max(hi, (int)atoms[t * w + k]); }
+        mn[t] = lo;
+        span = std::max(span, hi - lo);
+        order[t] = t;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return mn[a] < mn[b]; });
+    start.assign(n + 1, cnt);
+    int t = 0;
+    for (int a = 0; a <= n; ++a) {
+        while (t < cnt && mn[order[t]] < a) ++t;
+        start[a] = t;
+    }
+}
+
+long long count_samples(long long t_old, long long t_new, int t_gr) { return t_new / t_gr - t_old / t_gr; }
+
+} // namespace
+
+// ------------------------------------------------------------------ launches
+// forces of replicas [r_off, r_off + nrep) at their current positions.  Stepping calls
+// (force_build = 0) rely on k_integrate to clear the energies and maintain the list guard;
+// force-only calls (force_build = 1) rebuild the lists and clear the energies here.
+static gpr_status launch_forces(gpr_system *S, int r_off, int nrep, long long s, int energy, int apply_b, int force_build)
+{
+    const int BTB = 256, BTN = 256;
+    if (energy && force_build) {
+        HIPCHK(S, hipMemsetAsync(S->d.E + r_off, 0, sizeof(long long) * nrep, S->stream));
+    }
+    dim3 gb((S->n + BTB - 1) / BTB, nrep);
+    hipLaunchKernelGGL(k_bonded, gb, dim3(BTB), 3 * BTB * sizeof(long long), S->stream, S->d, r_off, energy);
+    LAUNCHCHK(S);
+    dim3 gn((S->n * P + BTN - 1) / BTN, nrep);
+    hipLaunchKernelGGL(k_nonbonded, gn, dim3(BTN), S->lds_nb, S->stream, S->d, s, r_off, energy, apply_b, force_build);
+    LAUNCHCHK(S);
+    return GPR_OK;
+}
+
+// advances replicas [0, nrep) by nsteps from local step counter t0; sample: accumulate the
+// observables of workers every t_gr; state_end: state ids at the end
+static gpr_status run_steps(gpr_system *S, int nrep, long long nsteps, long long t0, bool sample, bool state_end)
+{
+    if (nsteps <= 0) {
+        if (state_end) {
+            hipLaunchKernelGGL(k_state, dim3(nrep), dim3(256), S->lds_stage, S->stream, S->d, 0);
+            LAUNCHCHK(S);
+        }
+        return GPR_OK;
+    }
+    if (S->path == GPR_PATH_PERSISTENT) {
+        long long done = 0;
+        while (done < nsteps) {
+            const int chunk = (int)std::min<long long>(nsteps - done, 1 << 20);
+            const bool last = done + chunk == nsteps;
+            hipLaunchKernelGGL(k_persist, dim3(nrep), dim3(S->bt_persist), S->lds_persist, S->stream, S->d,
+                               S->s + done, chunk, (int)(t0 + done), sample ? 1 : 0, (state_end && last) ? 1 : 0);
+            LAUNCHCHK(S);
+            done += chunk;
+        }
+        S->s += nsteps;
+        return GPR_OK;
+    }
+    const int BTI = 256;
+    dim3 gi((S->n + BTI - 1) / BTI, nrep);
+    for (long long k = 0; k < nsteps; ++k) {
+        const long long tl = t0 + k + 1;
+        const bool samp = sample && nrep > 1 && (tl % S->t_gr == 0);
+        const int energy = (samp && S->d.need_energy) ? 1 : 0;
+        hipLaunchKernelGGL(k_integrate, gi, dim3(BTI), 0, S->stream, S->d, S->s, 0, energy);
+        LAUNCHCHK(S);
+        gpr_status rc = launch_forces(S, 0, nrep, S->s, energy, 1, 0);
+        if (rc) return rc;
+        S->s += 1;
+        if (samp) {
+            hipLaunchKernelGGL(k_obs, dim3(nrep - 1), dim3(256), S->lds_stage, S->stream, S->d, 1, 0, nullptr);
+            LAUNCHCHK(S);
+        }
+    }
+    if (state_end) {
+        hipLaunchKernelGGL(k_state, dim3(nrep), dim3(256), S->lds_stage, S->stream, S->d, 0);
+        LAUNCHCHK(S);
+    }
+    return GPR_OK;
+}
+
+static gpr_status check(gpr_system *S, int mode, int nrep, int check_index)
+{
+    hipLaunchKernelGGL(k_check, dim3(1), dim3(64), 0, S->stream, S->d, mode, S->s, S->omega, nrep, S->nsamp,
+                       check_index, S->st_dev, S->donor, S->surv, S->fec);
+    LAUNCHCHK(S);
+    if (mode == CHK_DEPHASE) {
+        hipLaunchKernelGGL(k_clone, dim3((3 * S->np + 255) / 256, nrep), dim3(256), 0, S->stream, S->d, S->donor, 1);
+        LAUNCHCHK(S);
+    }
+    HIPCHK(S, hipMemcpyAsync(S->st_host, S->st_dev, sizeof(Status), hipMemcpyDeviceToHost, S->stream));
+    HIPCHK(S, hipStreamSynchronize(S->stream));
+    if (S->st_host->err[ERR_UNSTABLE]) return fail(S, GPR_EUNSTABLE, "non-finite or overflowing state");
+    if (S->st_host->err[ERR_LIST]) return fail(S, GPR_EDEVICE, "pair-list capacity exceeded");
+    return GPR_OK;
+}
+
+static gpr_status copy_replica(gpr_system *S, int dst, int src)
+{
+    std::vector<int> dn(S->R, -1);
+    dn[dst] = src;
+    HIPCHK(S, hipMemcpyAsync(S->donor, dn.data(), sizeof(int) * S->R, hipMemcpyHostToDevice, S->stream));
+    hipLaunchKernelGGL(k_clone, dim3((3 * S->np + 255) / 256, S->R), dim3(256), 0, S->stream, S->d, S->donor, 0);
+    LAUNCHCHK(S);
+    return GPR_OK;
+}
+
+static gpr_status broadcast_reference(gpr_system *S)
+{
+    std::vector<int> dn(S->R, 0);
+    dn[0] = -1;
+    HIPCHK(S, hipMemcpyAsync(S->donor, dn.data(), sizeof(int) * S->R, hipMemcpyHostToDevice, S->stream));
+    hipLaunchKernelGGL(k_clone, dim3((3 * S->np + 255) / 256, S->R), dim3(256), 0, S->stream, S->d, S->donor, 1);
+    LAUNCHCHK(S);
+    return GPR_OK;
+}
+
+static gpr_status state_of_ref(gpr_system *S, int *out)
+{
+    gpr_status rc = run_steps(S, 1, 0, 0, false, true);
+    if (rc) return rc;
+    rc = check(S, CHK_STATE, 1, 0);
+    if (rc) return rc;
+    *out = S->st_host->to_state;
+    return GPR_OK;
+}
+
+// ------------------------------------------------------------------ create / destroy
+extern "C" void gpr_system_destroy(gpr_system *S)
+{
+    if (!S) return;
+    if (S->stream) hipStreamSynchronize(S->stream);
+    for (void *p : S->bufs) hipFree(p);
+    if (S->st_host) hipHostFree(S->st_host);
+    delete S;
+}
+
+extern "C" const char *gpr_last_error(const gpr_system *S)
+{
+    return S ? S->err.c_str() : g_thread_err.c_str();
+}
+
+static size_t persist_lds(int np)
+{
+    const int nblk = (np + BLK - 1) / BLK;
+    return (size_t)3 * np * 8 + (MAX_OBS * 8 + 8) * 8 + MAX_OBS * 8 + (size_t)np * 16 + (size_t)np * 8 + (size_t)nblk * 16;
+}
+
+static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
+{
+    const int n = D->n_atoms, R = D->n_replicas;
+    S->n = n; S->R = R; S->kind = D->kind;
+    S->np = (n + 63) / 64 * 64;
+    const int np = S->np;
+    S->t_gr = D->t_gr; S->tcd = D->t_check_dephase; S->tcp = D->t_check_parallel;
+    S->tol = D->tol; S->dt = D->dt; S->t_min = D->t_min; S->kT = D->kT;
+    S->nobs = D->n_obs;
+    Dev &d = S->d;
+    d.kind = D->kind; d.n = n; d.np = np; d.R = R;
+
+    // per-atom parameters
+    const double c1 = std::exp(-D->gamma * D->dt);
+    const double c2 = std::sqrt(std::max(0.0, 1.0 - c1 * c1));
+    std::vector<float4> prm(np, make_float4(0, 0, 0, 0));
+    std::vector<float> sd(np, 0.f), mass(np, 0.f);
+    for (int i = 0; i < n; ++i) {
+        const double sig = D->kind == GPR_KIND_MOLECULAR ? D->sigma[i] : 0.0;
+        const double eps = D->kind == GPR_KIND_MOLECULAR ? D->epsilon[i] : 0.0;
+        const double q = D->kind == GPR_KIND_MOLECULAR ? D->charge[i] : 0.0;
+        prm[i] = make_float4((float)(0.5 * sig), (float)(2.0 * std::sqrt(eps)), (float)(q * std::sqrt(COULOMB_F)),
+                             (float)(1.0 / D->mass[i]));
+        sd[i] = (float)(c2 * std::sqrt(D->kT / D->mass[i]));
+        mass[i] = (float)D->mass[i];
+    }
+    HIPCHK(S, upload(S, (float4 **)&d.prm, prm));
+    HIPCHK(S, upload(S, (float **)&d.sd, sd));
+    HIPCHK(S, upload(S, (float **)&d.mass, mass));
+
+    // exclusions (and 1-4 pairs) as bit masks over index offsets -32..31
+    std::vector<unsigned long long> excl(np, 0ull);
+    auto mark = [&](int i, int j) -> bool {
+        const int off = j - i;
+        if (off < -32 || off >= 32 || off == 0) return off == 0;
+        excl[i] |= 1ull << (off + 32);
+        excl[j] |= 1ull << (-off + 32);
+        return true;
+    };
+    if (D->kind == GPR_KIND_MOLECULAR) {
+        for (int e = 0; e < D->n_exclusions; ++e)
+            if (!mark(D->exclusion_atoms[2 * e], D->exclusion_atoms[2 * e + 1]) ||
+                D->exclusion_atoms[2 * e + 1] - D->exclusion_atoms[2 * e] == 32)
+                return fail(S, GPR_EINVAL, "exclusion between atoms more than 32 indices apart");
+        for (int p = 0; p < D->n_pairs14; ++p)
+            if (!mark(D->pair14_atoms[2 * p], D->pair14_atoms[2 * p + 1]) ||
+                D->pair14_atoms[2 * p + 1] - D->pair14_atoms[2 * p] == 32)
+                return fail(S, GPR_EINVAL, "1-4 pair between atoms more than 32 indices apart");
+    }
+    HIPCHK(S, upload(S, (unsigned long long **)&d.excl, excl));
+
+    // replica state: every replica starts from (pos, vel)
+    const size_t rs = (size_t)R * 3 * np;
+    std::vector<float> x0(3 * np, 0.f), v0(3 * np, 0.f);
+    for (int c = 0; c < 3; ++c)
+        for (int i = 0; i < n; ++i) {
+            x0[c * np + i] = (float)D->pos[c * n + i];
+            if (D->vel) v0[c * np + i] = (float)D->vel[c * n + i];
+        }
+    if (D->kind == GPR_KIND_TOY2D) { x0[2 * np] = 0.f; v0[2 * np] = 0.f; }
+    HIPCHK(S, dalloc(S, &d.x, rs));
+    HIPCHK(S, dalloc(S, &d.v, rs));
+    HIPCHK(S, dalloc(S, &d.xb, rs));
+    HIPCHK(S, dalloc(S, &d.F, rs));
+    HIPCHK(S, dalloc(S, &d.E, R));
+    HIPCHK(S, hipMemcpy(d.x, x0.data(), sizeof(float) * 3 * np, hipMemcpyHostToDevice));
+    HIPCHK(S, hipMemcpy(d.v, v0.data(), sizeof(float) * 3 * np, hipMemcpyHostToDevice));
+
+    // bonded topology, each type sorted by smallest atom
+    Topo &T = d.tp;
+    std::vector<int> order, start;
+    if (D->kind == GPR_KIND_MOLECULAR) {
+        {
+            sort_terms(D->bond_atoms, D->n_bonds, 2, n, order, start, T.b_span);
+            std::vector<int2> ij(D->n_bonds); std::vector<float2> p(D->n_bonds);
+            for (int k = 0; k < D->n_bonds; ++k) {
+                const int t = order[k];
+                ij[k] = make_int2(D->bond_atoms[2 * t], D->bond_atoms[2 * t + 1]);
+                p[k] = make_float2((float)D->bond_r0[t], (float)D->bond_k[t]);
+            }
+            T.nb = D->n_bonds;
+            HIPCHK(S, upload(S, (int2 **)&T.b_ij, ij)); HIPCHK(S, upload(S, (float2 **)&T.b_p, p));
+            HIPCHK(S, upload(S, (int **)&T.b_start, start));
+        }
+        {
+            sort_terms(D->angle_atoms, D->n_angles, 3, n, order, start, T.a_span);
+            std::vector<int4> ijk(D->n_angles); std::vector<float2> p(D->n_angles);
+            for (int k = 0; k < D->n_angles; ++k) {
+                const int t = order[k];
+                ijk[k] = make_int4(D->angle_atoms[3 * t], D->angle_atoms[3 * t + 1], D->angle_atoms[3 * t + 2], 0);
+                p[k] = make_float2((float)D->angle_theta0[t], (float)D->angle_k[t]);
+            }
+            T.na = D->n_angles;
+            HIPCHK(S, upload(S, (int4 **)&T.a_ijk, ijk)); HIPCHK(S, upload(S, (float2 **)&T.a_p, p));
+            HIPCHK(S, upload(S, (int **)&T.a_start, start));
+        }
+        {
+            sort_terms(D->torsion_atoms, D->n_torsions, 4, n, order, start, T.t_span);
+            std::vector<int4> q(D->n_torsions); std::vector<float4> p(D->n_torsions);
+            for (int k = 0; k < D->n_torsions; ++k) {
+                const int t = order[k];
+                q[k] = make_int4(D->torsion_atoms[4 * t], D->torsion_atoms[4 * t + 1], D->torsion_atoms[4 * t + 2],
+                                 D->torsion_atoms[4 * t + 3]);
+                p[k] = make_float4((float)D->torsion_k[t], (float)D->torsion_phi0[t], (float)D->torsion_n[t], 0.f);
+            }
+            T.nt = D->n_torsions;
+            HIPCHK(S, upload(S, (int4 **)&T.t_ijkl, q)); HIPCHK(S, upload(S, (float4 **)&T.t_p, p));
+            HIPCHK(S, upload(S, (int **)&T.t_start, start));
+        }
+        {
+            int span0 = 0;
+            sort_terms(D->restraint_atom, D->n_restraints, 1, n, order, start, span0);
+            std::vector<int> ia(D->n_restraints); std::vector<float4> p(D->n_restraints);
+            for (int k = 0; k < D->n_restraints; ++k) {
+                const int t = order[k];
+                ia[k] = D->restraint_atom[t];
+                p[k] = make_float4((float)D->restraint_ref[3 * t], (float)D->restraint_ref[3 * t + 1],
+                                   (float)D->restraint_ref[3 * t + 2], (float)D->restraint_k[t]);
+            }
+            T.nr = D->n_restraints;
+            HIPCHK(S, upload(S, (int **)&T.r_i, ia)); HIPCHK(S, upload(S, (float4 **)&T.r_p, p));
+            HIPCHK(S, upload(S, (int **)&T.r_start, start));
+        }
+        {
+            sort_terms(D->pair14_atoms, D->n_pairs14, 2, n, order, start, T.p_span);
+            std::vector<int2> ij(D->n_pairs14); std::vector<float4> p(D->n_pairs14);
+            for (int k = 0; k < D->n_pairs14; ++k) {
+                const int t = order[k];
+                const int i = D->pair14_atoms[2 * t], j = D->pair14_atoms[2 * t + 1];
+                ij[k] = make_int2(i, j);
+                const double sij = 0.5 * (D->sigma[i] + D->sigma[j]);
+                const double eij = std::sqrt(D->epsilon[i] * D->epsilon[j]);
+                p[k] = make_float4((float)sij, (float)(4.0 * eij * D->scale14),
+                                   (float)(COULOMB_F * D->charge[i] * D->charge[j] * D->scale14), 0.f);
+            }
+            T.n14 = D->n_pairs14;
+            HIPCHK(S, upload(S, (int2 **)&T.p_ij, ij)); HIPCHK(S, upload(S, (float4 **)&T.p_p, p));
+            HIPCHK(S, upload(S, (int **)&T.p_start, start));
+        }
+    }
+
+    // nonbonded constants and pair-list capacity
+    d.cutoff_on = (D->kind == GPR_KIND_MOLECULAR && D->cutoff > 0) ? 1 : 0;
+    if (d.cutoff_on) {
+        const double rc = D->cutoff;
+        const double krf = (D->eps_rf - 1.0) / ((2.0 * D->eps_rf + 1.0) * rc * rc * rc);
+        d.rc2 = (float)(rc * rc);
+        d.krf = (float)krf;
+        d.crf = (float)(1.0 / rc + krf * rc * rc);
+        d.rl = (float)(rc + D->skin + 1e-4);
+        d.rl2 = d.rl * d.rl;
+        d.half_skin2 = (float)(0.25 * D->skin * D->skin);
+        d.period = std::max(1, D->nlist_period);
+    } else {
+        d.rc2 = INFINITY; d.krf = 0.f; d.crf = 0.f; d.rl = INFINITY; d.rl2 = INFINITY;
+        d.half_skin2 = INFINITY; d.period = 1 << 30;
+    }
+    // capacity from the initial structure: the largest sub-list within r_list, doubled
+    int maxsub = 0;
+    if (D->kind == GPR_KIND_MOLECULAR) {
+        const double rl2 = d.cutoff_on ? (double)d.rl * d.rl * 1.21 : INFINITY;
+        std::vector<int> cnt(P);
+        for (int i = 0; i < n; ++i) {
+            std::fill(cnt.begin(), cnt.end(), 0);
+            for (int j = 0; j < n; ++j) {
+                if (j == i) continue;
+                const double dx = D->pos[i] - D->pos[j], dy = D->pos[n + i] - D->pos[n + j], dz = D->pos[2 * n + i] - D->pos[2 * n + j];
+                if (dx * dx + dy * dy + dz * dz < rl2) cnt[j % P]++;
+            }
+            for (int q = 0; q < P; ++q) maxsub = std::max(maxsub, cnt[q]);
+        }
+    }
+    d.K = std::min(65535, std::max(8, d.cutoff_on ? 2 * maxsub + 8 : maxsub + 1));
+    HIPCHK(S, dalloc(S, &d.nbl, (size_t)R * d.K * np * P));
+    HIPCHK(S, dalloc(S, &d.nbc, (size_t)R * np * P));
+    HIPCHK(S, dalloc(S, &d.guard, 2 * R));
+    HIPCHK(S, dalloc(S, &d.need_build, R));
+    HIPCHK(S, dalloc(S, &d.err, 4));
+    HIPCHK(S, dalloc(S, &d.acc, (size_t)R * MAX_OBS * 2));
+    HIPCHK(S, dalloc(S, &d.shift, MAX_OBS));
+    HIPCHK(S, dalloc(S, &d.state, R));
+
+    // states and observables with their atom groups
+    std::vector<int> groups;
+    auto add_group = [&](const int32_t *g, int cnt, int &off, double &mtot) {
+        off = (int)groups.size();
+        mtot = 0;
+        for (int k = 0; k < cnt; ++k) { groups.push_back(g[k]); mtot += D->mass[g[k]]; }
+    };
+    StateDesc &st = d.st;
+    st.kind = D->state.kind;
+    for (int k = 0; k < 8; ++k) st.atoms[k] = D->state.atoms[k];
+    st.nbox = D->state.n_boxes;
+    for (int b = 0; b < GPR_MAX_BOXES; ++b)
+        for (int c = 0; c < 4; ++c) st.box[b][c] = D->state.box[b][c];
+    for (int c = 0; c < 3; ++c) st.center[c] = D->state.center[c];
+    st.radius = D->state.radius;
+    st.g_n = D->state.kind == GPR_STATE_COM_SPHERE ? D->state.n_group : 0;
+    add_group(D->state.group, st.g_n, st.g_off, st.gm);
+    d.nobs = D->n_obs;
+    d.need_energy = 0;
+    for (int j = 0; j < D->n_obs; ++j) {
+        const gpr_obs_desc &o = D->obs[j];
+        ObsDesc &od = d.obs[j];
+        od.kind = o.kind;
+        for (int k = 0; k < 4; ++k) od.atoms[k] = o.atoms[k];
+        od.ga_n = (o.kind == GPR_OBS_COM_DISTANCE || o.kind == GPR_OBS_RMS_VELOCITY) ? o.n_a : 0;
+        od.gb_n = o.kind == GPR_OBS_COM_DISTANCE ? o.n_b : 0;
+        add_group(o.group_a, od.ga_n, od.ga_off, od.ma);
+        add_group(o.group_b, od.gb_n, od.gb_off, od.mb);
+        if (o.kind == GPR_OBS_POTENTIAL) d.need_energy = 1;
+    }
+    HIPCHK(S, upload(S, (int **)&d.groups, groups));
+
+    d.h = (float)(0.5 * D->dt);
+    d.c1 = (float)c1;
+    d.key0 = (uint32_t)D->seed;
+    d.key1 = (uint32_t)(D->seed >> 32);
+    d.t_gr = D->t_gr;
+
+    // scratch for the per-check bookkeeping
+    HIPCHK(S, dalloc(S, &S->st_dev, 1));
+    HIPCHK(S, hipHostMalloc((void **)&S->st_host, sizeof(Status), hipHostMallocDefault));
+    HIPCHK(S, dalloc(S, &S->donor, R));
+    HIPCHK(S, dalloc(S, &S->surv, R));
+    HIPCHK(S, dalloc(S, &S->fec, R));
+    HIPCHK(S, dalloc(S, &S->obs_out, (size_t)R * MAX_OBS));
+
+    // LDS budgets
+    const int nblk = (n + BLK - 1) / BLK;
+    S->lds_nb = (size_t)np * 24 + (size_t)nblk * 16;
+    S->lds_stage = (size_t)np * 16;
+    S->lds_persist = persist_lds(np);
+    int dev = 0, maxlds = 0;
+    HIPCHK(S, hipGetDevice(&dev));
+    HIPCHK(S, hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    if ((int)S->lds_nb > maxlds || (int)S->lds_stage > maxlds)
+        return fail(S, GPR_EINVAL, "system too large for the LDS-staged pair kernel");
+    HIPCHK(S, hipFuncSetAttribute((const void *)k_nonbonded, hipFuncAttributeMaxDynamicSharedMemorySize, (int)S->lds_nb));
+    HIPCHK(S, hipFuncSetAttribute((const void *)k_obs, hipFuncAttributeMaxDynamicSharedMemorySize, (int)S->lds_stage));
+    HIPCHK(S, hipFuncSetAttribute((const void *)k_state, hipFuncAttributeMaxDynamicSharedMemorySize, (int)S->lds_stage));
+    S->persist_ok = (int)S->lds_persist <= maxlds;
+    if (S->persist_ok) {
+        HIPCHK(S, hipFuncSetAttribute((const void *)k_persist, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)S->lds_persist));
+    }
+    const int want = std::min(1024, std::max(64, (n * P + 63) / 64 * 64));
+    S->bt_persist = want;
+    while ((n + S->bt_persist - 1) / S->bt_persist > CHMAX && S->bt_persist < 1024) S->bt_persist += 64;
+    if ((n + S->bt_persist - 1) / S->bt_persist > CHMAX) S->persist_ok = 0;
+
+    // initial velocities, copies into every replica, forces, Omega and the observable shift
+    if (!D->vel) {
+        hipLaunchKernelGGL(k_init_vel, dim3((n + 255) / 256), dim3(256), 0, S->stream, S->d, (float)D->kT);
+        LAUNCHCHK(S);
+    }
+    gpr_status rc = launch_forces(S, 0, 1, -1, 1, 0, 1);
+    if (rc) return rc;
+    rc = broadcast_reference(S);
+    if (rc) return rc;
+    HIPCHK(S, hipMemsetAsync(d.need_build, 0, sizeof(int) * R, S->stream));
+    rc = launch_forces(S, 0, R, -1, 1, 0, 1);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_obs, dim3(1), dim3(256), S->lds_stage, S->stream, S->d, 0, 1, nullptr);
+    LAUNCHCHK(S);
+    rc = state_of_ref(S, &S->omega);
+    if (rc) return rc;
+    S->phase = PH_IDLE;
+    return GPR_OK;
+}
+
+extern "C" gpr_status gpr_system_create(const gpr_system_desc *D, gpr_system **out)
+{
+    if (!out) return fail(nullptr, GPR_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!D) return fail(nullptr, GPR_EINVAL, "descriptor is NULL");
+    if (D->kind != GPR_KIND_TOY2D && D->kind != GPR_KIND_MOLECULAR) return fail(nullptr, GPR_EINVAL, "bad kind");
+    if (D->n_atoms < 1 || D->n_atoms > 65535 || D->n_replicas < 2 || !D->mass || !D->pos)
+        return fail(nullptr, GPR_EINVAL, "bad sizes or missing arrays");
+    if (D->kind == GPR_KIND_TOY2D && D->n_atoms != 1) return fail(nullptr, GPR_EINVAL, "the toy system has one particle");
+    if (!(D->dt > 0) || !(D->kT > 0) || !(D->gamma >= 0)) return fail(nullptr, GPR_EINVAL, "bad dynamics parameters");
+    if (D->t_gr < 1 || D->t_check_dephase < 1 || D->t_check_parallel < 1) return fail(nullptr, GPR_EINVAL, "bad periods");
+    if (D->n_obs < 0 || D->n_obs > GPR_MAX_OBS || (D->n_obs > 0 && !D->obs)) return fail(nullptr, GPR_EINVAL, "bad observables");
+    const int n = D->n_atoms;
+    for (int i = 0; i < n; ++i) if (!(D->mass[i] > 0)) return fail(nullptr, GPR_EINVAL, "mass <= 0");
+    if (D->kind == GPR_KIND_MOLECULAR) {
+        if (!D->sigma || !D->epsilon || !D->charge) return fail(nullptr, GPR_EINVAL, "missing nonbonded parameters");
+        if (!idx_ok(D->bond_atoms, 2L * D->n_bonds, n) || !idx_ok(D->angle_atoms, 3L * D->n_angles, n) ||
+            !idx_ok(D->torsion_atoms, 4L * D->n_torsions, n) || !idx_ok(D->restraint_atom, D->n_restraints, n) ||
+            !idx_ok(D->pair14_atoms, 2L * D->n_pairs14, n) || !idx_ok(D->exclusion_atoms, 2L * D->n_exclusions, n))
+            return fail(nullptr, GPR_EINVAL, "term atom index out of range");
+        if ((D->n_bonds && (!D->bond_r0 || !D->bond_k)) || (D->n_angles && (!D->angle_theta0 || !D->angle_k)) ||
+            (D->n_torsions && (!D->torsion_n || !D->torsion_k || !D->torsion_phi0)) ||
+            (D->n_restraints && (!D->restraint_ref || !D->restraint_k)))
+            return fail(nullptr, GPR_EINVAL, "missing term parameters");
+        if (D->cutoff > 0 && (!(D->skin > 0) || !(D->eps_rf >= 1))) return fail(nullptr, GPR_EINVAL, "bad cutoff parameters");
+    }
+    const gpr_state_desc &st = D->state;
+    if (st.kind == GPR_STATE_SIGN_X) {
+        if (!idx_ok(st.atoms, 1, n)) return fail(nullptr, GPR_EINVAL, "bad state atom");
+    } else if (st.kind == GPR_STATE_DIHEDRAL_BOXES) {
+        if (!idx_ok(st.atoms, 8, n) || st.n_boxes < 1 || st.n_boxes > GPR_MAX_BOXES) return fail(nullptr, GPR_EINVAL, "bad state boxes");
+    } else if (st.kind == GPR_STATE_COM_SPHERE) {
+        if (st.n_group < 1 || !idx_ok(st.group, st.n_group, n)) return fail(nullptr, GPR_EINVAL, "bad state group");
+    } else {
+        return fail(nullptr, GPR_EINVAL, "bad state kind");
+    }
+    for (int j = 0; j < D->n_obs; ++j) {
+        const gpr_obs_desc &o = D->obs[j];
+        bool ok = true;
+        switch (o.kind) {
+        case GPR_OBS_COORD: ok = idx_ok(o.atoms, 1, n) && o.atoms[1] >= 0 && o.atoms[1] <= 2; break;
+        case GPR_OBS_POTENTIAL: case GPR_OBS_KINETIC: break;
+        case GPR_OBS_DIHEDRAL: ok = idx_ok(o.atoms, 4, n); break;
+        case GPR_OBS_COM_DISTANCE: ok = o.n_a >= 1 && o.n_b >= 1 && idx_ok(o.group_a, o.n_a, n) && idx_ok(o.group_b, o.n_b, n); break;
+        case GPR_OBS_RMS_VELOCITY: ok = o.n_a >= 1 && idx_ok(o.group_a, o.n_a, n); break;
+        default: ok = false;
+        }
+        if (!ok) return fail(nullptr, GPR_EINVAL, "bad observable");
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(nullptr, GPR_EDEVICE, "no HIP device");
+    gpr_system *S = new (std::nothrow) gpr_system();
+    if (!S) return fail(nullptr, GPR_ENOMEM, "host allocation failed");
+    gpr_status rc = create_impl(D, S);
+    if (rc != GPR_OK) {
+        g_thread_err = S->err;
+        gpr_system_destroy(S);
+        return rc;
+    }
+    *out = S;
+    return GPR_OK;
+}
+
+extern "C" gpr_status gpr_set_stream(gpr_system *S, void *stream)
+{
+    if (!S) return fail(nullptr, GPR_EINVAL, "NULL system");
+    HIPCHK(S, hipStreamSynchronize(S->stream));
+    S->stream = (hipStream_t)stream;
+    return GPR_OK;
+}
+
+extern "C" gpr_status gpr_set_path(gpr_system *S, int32_t path)
+{
+    if (!S) return fail(nullptr, GPR_EINVAL, "NULL system");
+    if (path != GPR_PATH_PLAIN && path != GPR_PATH_PERSISTENT) return fail(S, GPR_EINVAL, "bad path");
+    if (path == GPR_PATH_PERSISTENT && !S->persist_ok) return fail(S, GPR_EINVAL, "system too large for the persistent path");
+    S->path = path;
+    return GPR_OK;
+}
+
+extern "C" gpr_status gpr_set_launch(gpr_system *S, int32_t block_threads, int32_t groups_per_replica)
+{
+    if (!S) return fail(nullptr, GPR_EINVAL, "NULL system");
+    if (groups_per_replica != 0 && groups_per_replica != 1) return fail(S, GPR_EINVAL, "groups_per_replica must be 1");
+    if (block_threads != 0) {
+        if (block_threads < 64 || block_threads > 1024 || block_threads % 64)
+            return fail(S, GPR_EINVAL, "block_threads must be a multiple of 64 in [64, 1024]");
+        if ((S->n + block_threads - 1) / block_threads > CHMAX) return fail(S, GPR_EINVAL, "block too small for the system");
+        S->bt_persist = block_threads;
+    }
+    return GPR_OK;
+}
+
+// ------------------------------------------------------------------ queries
+extern "C" double gpr_simulated_time(const gpr_system *S) { return S ? (double)S->tsim * S->dt : NAN; }
+extern "C" int64_t gpr_simulated_steps(const gpr_system *S) { return S ? S->tsim : -1; }
+extern "C" int64_t gpr_global_step(const gpr_system *S) { return S ? S->s : -1; }
+extern "C" int32_t gpr_current_state(const gpr_system *S) { return S ? S->omega : INT32_MIN; }
+
+extern "C" gpr_status gpr_energy_forces(gpr_system *S, int32_t r0, int32_t nr, double *energy, double *forces)
+{
+    if (!S) return fail(nullptr, GPR_EINVAL, "NULL system");
+    if (r0 < 0 || nr < 0 || r0 + nr > S->R) return fail(S, GPR_EINVAL, "replica range");
+    if (nr == 0) return GPR_OK;
+    gpr_status rc = launch_forces(S, r0, nr, -1, 1, 0, 1);
+    if (rc) return rc;
+    std::vector<long long> F((size_t)nr * 3 * S->np), E(nr);
+    HIPCHK(S, hipMemcpyAsync(F.data(), S->d.F + (size_t)r0 * 3 * S->np, F.size() * 8, hipMemcpyDeviceToHost, S->stream));
+    HIPCHK(S, hipMemcpyAsync(E.data(), S->d.E + r0, E.size() * 8, hipMemcpyDeviceToHost, S->stream));
+    int err[4];
+    HIPCHK(S, hipMemcpyAsync(err, S->d.err, sizeof err, hipMemcpyDeviceToHost, S->stream));
+    HIPCHK(S, hipStreamSynchronize(S->stream));
+    if (err[ERR_LIST]) return fail(S, GPR_EDEVICE, "pair-list capacity exceeded");
+    for (int k = 0; k < nr; ++k) {
+        if (energy) energy[k] = (double)E[k] * FIX_INV;
+        if (forces)
+            for (int c = 0; c < 3; ++c)
+                for (int i = 0; i < S->n; ++i)
+                    forces[((size_t)k * 3 + c) * S->n + i] = (double)F[((size_t)k * 3 + c) * S->np + i] * FIX_INV;
+    }
+    return GPR_OK;
+}
+
+extern "C" gpr_status gpr_get_state(const gpr_system *Sc, int32_t r, double *q, double *v)
+{
+    gpr_system *S = const_cast<gpr_system *>(Sc);
+    if (!S) return fail(nullptr, GPR_EINVAL, "NULL system");
+    if (r < 0 || r >= S->R) return fail(S, GPR_EINVAL, "replica index");
+    std::vector<float> x(3 * S->np), vv(3 * S->np);
+    HIPCHK(S, hipMemcpyAsync(x.data(), S->d.x + (size_t)r * 3 * S->np, x.size() * 4, hipMemcpyDeviceToHost, S->stream));
+    HIPCHK(S, hipMemcpyAsync(vv.data(), S->d.v + (size_t)r * 3 * S->np, vv.size() * 4, hipMemcpyDeviceToHost, S->stream));
+    HIPCHK(S, hipStreamSynchronize(S->stream));
+    for (int c = 0; c < 3; ++c)
+        for (int i = 0; i < S->n; ++i) {
+            if (q) q[c * S->n + i] = x[c * S->np + i];
+            if (v) v[c * S->n + i] = vv[c * S->np + i];
+        }
+    return GPR_OK;
+}
+
+extern "C" gpr_status gpr_set_state(gpr_system *S, int32_t r, const double *q, const double *v)
+{
+    if (!S) return fail(nullptr, GPR_EINVAL, "NULL system");
+    if (r < 0 || r >= S->R || !q) return fail(S, GPR_EINVAL, "replica index or NULL positions");
+    std::vector<float> x(3 * S->np, 0.f), vv(3 * S->np, 0.f);
+    if (!v) {
+        HIPCHK(S, hipMemcpyAsync(vv.data(), S->d.v + (size_t)r * 3 * S->np, vv.size() * 4, hipMemcpyDeviceToHost, S->stream));
+        HIPCHK(S, hipStreamSynchronize(S->stream));
+    }
+    for (int c = 0; c < 3; ++c)
+        for (int i = 0; i < S->n; ++i) {
+            x[c * S->np + i] = (float)q[c * S->n + i];
+            if (v) vv[c * S->np + i] = (float)v[c * S->n + i];
+        }
+    if (S->kind == GPR_KIND_TOY2D) { x[2 * S->np] = 0.f; vv[2 * S->np] = 0.f; }
+    HIPCHK(S, hipMemcpyAsync(S->d.x + (size_t)r * 3 * S->np, x.data(), x.size() * 4, hipMemcpyHostToDevice, S->stream));
+    HIPCHK(S, hipMemcpyAsync(S->d.v + (size_t)r * 3 * S->np, vv.data(), vv.size() * 4, hipMemcpyHostToDevice, S->stream));
+    gpr_status rc = launch_forces(S, r, 1, -1, 1, 0, 1);
+    if (rc) return rc;
+    HIPCHK(S, hipStreamSynchronize(S->stream));
+    S->phase = PH_IDLE;
+    return GPR_OK;
+}
+
+extern "C" gpr_status gpr_get_accumulators(const gpr_system *Sc, int64_t *n, double *S1, double *S2, double *shift)
+{
+    gpr_system *S = const_cast<gpr_system *>(Sc);
+    if (!S) return fail(nullptr, GPR_EINVAL, "NULL system");
+    std::vector<double> acc((size_t)S->R * MAX_OBS * 2), sh(MAX_OBS);
+    HIPCHK(S, hipMemcpyAsync(acc.data(), S->d.acc, acc.size() * 8, hipMemcpyDeviceToHost, S->stream));
+    HIPCHK(S, hipMemcpyAsync(sh.data(), S->d.shift, sh.size() * 8, hipMemcpyDeviceToHost, S->stream));
+    HIPCHK(S, hipStreamSynchronize(S->stream));
+    if (n) *n = S->nsamp;
+    for (int r = 0; r < S->R; ++r)
+        for (int j = 0; j < S->nobs; ++j) {
+            if (S1) S1[r * S->nobs + j] = acc[((size_t)r * MAX_OBS + j) * 2];
+            if (S2) S2[r * S->nobs + j] = acc[((size_t)r * MAX_OBS + j) * 2 + 1];
+        }
+    if (shift) for (int j = 0; j < S->nobs; ++j) shift[j] = sh[j];
+    return GPR_OK;
+}
+
+extern "C" gpr_status gpr_observe(gpr_system *S, double *obs, int32_t *state)
+{
+    if (!S) return fail(nullptr, GPR_EINVAL, "NULL system");
+    if (S->d.need_energy) {
+        gpr_status rc = launch_forces(S, 0, S->R, -1, 1, 0, 1);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_obs, dim3(S->R), dim3(256), S->lds_stage, S->stream, S->d, 0, 2, S->obs_out);
+    LAUNCHCHK(S);
+    hipLaunchKernelGGL(k_state, dim3(S->R), dim3(256), S->lds_stage, S->stream, S->d, 0);
+    LAUNCHCHK(S);
+    std::vector<double> h((size_t)S->R * MAX_OBS);
+    std::vector<int> st(S->R);
+    HIPCHK(S, hipMemcpyAsync(h.data(), S->obs_out, h.size() * 8, hipMemcpyDeviceToHost, S->stream));
+    HIPCHK(S, hipMemcpyAsync(st.data(), S->d.state, st.size() * 4, hipMemcpyDeviceToHost, S->stream));
+    HIPCHK(S, hipStreamSynchronize(S->stream));
+    for (int r = 0; r < S->R; ++r) {
+        if (obs) for (int j = 0; j < S->nobs; ++j) obs[r * S->nobs + j] = h[(size_t)r * MAX_OBS + j];
+        if (state) state[r] = st[r];
+    }
+    return GPR_OK;
+}
+
+// ------------------------------------------------------------------ Gen.ParRep steps
+extern "C" gpr_status gpr_decorrelate(gpr_system *S, int64_t t_corr, int64_t max_steps, gpr_event *ev)
+{
+    if (!S || !ev) return fail(S, GPR_EINVAL, "NULL argument");
+    gpr_status rc;
+    if (S->phase != PH_DECORR) {
+        int st0 = -1;
+        rc = state_of_ref(S, &st0);
+        if (rc) return rc;
+        S->phase = PH_DECORR;
+        S->dc_omega = st0;
+        S->dc_from = st0;
+        S->dc_resid = 0;
+        S->dc_steps = 0;
+    }
+    long long taken = 0;
+    for (;;) {
+        if (S->dc_omega != -1 && S->dc_resid >= t_corr) {
+            S->omega = S->dc_omega;
+            S->phase = PH_IDLE;
+            ev->kind = GPR_EV_RESIDENT; ev->from_state = S->dc_from; ev->to_state = S->dc_omega; ev->pad = 0;
+            ev->resident_steps = S->dc_resid; ev->steps_taken = S->dc_steps;
+            return GPR_OK;
+        }
+        if (taken >= max_steps) return GPR_BUDGET;
+        rc = run_steps(S, 1, S->tcd, 0, false, true);
+        if (rc) return rc;
+        S->tsim += S->tcd;
+        taken += S->tcd;
+        S->dc_steps += S->tcd;
+        rc = check(S, CHK_STATE, 1, 0);
+        if (rc) return rc;
+        const int st = S->st_host->to_state;
+        if (st == S->dc_omega) {
+            S->dc_resid += S->tcd;
+        } else if (S->dc_omega == -1) {
+            S->dc_omega = st;
+            S->dc_resid = 0;
+        } else {
+            ev->kind = GPR_EV_EXITED; ev->from_state = S->dc_omega; ev->to_state = st; ev->pad = 0;
+            ev->resident_steps = S->dc_resid + S->tcd; ev->steps_taken = S->dc_steps;
+            S->omega = st;
+            S->phase = PH_IDLE;
+            return GPR_OK;
+        }
+    }
+}
+
+extern "C" gpr_status gpr_dephase(gpr_system *S, int64_t max_steps, gpr_dephase_out *o)
+{
+    if (!S || !o) return fail(S, GPR_EINVAL, "NULL argument");
+    gpr_status rc;
+    if (S->phase != PH_DEPHASE) {
+        if (S->omega == -1) return fail(S, GPR_EPHASE, "reference walker is in no state");
+        rc = broadcast_reference(S);
+        if (rc) return rc;
+        HIPCHK(S, hipMemsetAsync(S->d.acc, 0, sizeof(double) * S->R * MAX_OBS * 2, S->stream));
+        if (S->d.need_energy) {
+            rc = launch_forces(S, 0, 1, -1, 1, 0, 1);
+            if (rc) return rc;
+        }
+        hipLaunchKernelGGL(k_obs, dim3(1), dim3(256), S->lds_stage, S->stream, S->d, 0, 1, nullptr);
+        LAUNCHCHK(S);
+        S->nsamp = 0;
+        S->dp_t = 0;
+        S->n_branch = 0;
+        S->phase = PH_DEPHASE;
+    }
+    long long taken = 0;
+    while (taken < max_steps) {
+        const long long k = std::min<long long>(S->tcd - S->dp_t % S->tcd, max_steps - taken);
+        const bool at_check = (S->dp_t + k) % S->tcd == 0;
+        rc = run_steps(S, S->R, k, S->dp_t, true, at_check);
+        if (rc) return rc;
+        S->nsamp += count_samples(S->dp_t, S->dp_t + k, S->t_gr);
+        S->dp_t += k;
+        taken += k;
+        if (!at_check) break;
+        rc = check(S, CHK_DEPHASE, S->R, 0);
+        if (rc) return rc;
+        const Status &st = *S->st_host;
+        if (st.ref_exited) {
+            S->tsim += S->dp_t;
+            o->outcome = GPR_DEPHASE_REF_EXITED; o->to_state = st.to_state; o->t_steps = S->dp_t;
+            o->n_branch = S->n_branch; o->n_samples = S->nsamp;
+            for (int j = 0; j < GPR_MAX_OBS; ++j) o->rhat[j] = j < S->nobs ? st.rhat[j] : 0.0;
+            S->omega = st.to_state;
+            S->phase = PH_IDLE;
+            return GPR_OK;
+        }
+        if (st.n_surv == 0 && S->R > 1) {
+            S->n_branch += S->R - 1;
+            S->nsamp = 0;
+        } else {
+            S->n_branch += st.n_exited;
+        }
+        bool conv = S->dp_t >= S->t_min && S->nsamp >= 2;
+        for (int j = 0; j < S->nobs && conv; ++j) conv = st.rhat[j] < 1.0 + S->tol;
+        if (conv) {
+            S->tsim += S->dp_t;
+            o->outcome = GPR_DEPHASE_CONVERGED; o->to_state = S->omega; o->t_steps = S->dp_t;
+            o->n_branch = S->n_branch; o->n_samples = S->nsamp;
+            for (int j = 0; j < GPR_MAX_OBS; ++j) o->rhat[j] = j < S->nobs ? st.rhat[j] : 0.0;
+            S->phase = PH_CONVERGED;
+            return GPR_OK;
+        }
+    }
+    return GPR_BUDGET;
+}
+
+extern "C" gpr_status gpr_parallel_step(gpr_system *S, int64_t max_checks, gpr_exit_out *o)
+{
+    if (!S || !o) return fail(S, GPR_EINVAL, "NULL argument");
+    if (S->phase == PH_CONVERGED) { S->phase = PH_PARALLEL; S->par_M = 0; }
+    else if (S->phase != PH_PARALLEL) return fail(S, GPR_EPHASE, "parallel step needs a converged dephasing");
+    long long checks = 0;
+    while (checks < max_checks) {
+        gpr_status rc = run_steps(S, S->R, S->tcp, 0, false, true);
+        if (rc) return rc;
+        S->par_M += 1;
+        checks += 1;
+        rc = check(S, CHK_PARALLEL, S->R, 0);
+        if (rc) return rc;
+        const int k = S->st_host->k;
+        if (k == 0) continue;
+        const long long tau = ((long long)S->R * (S->par_M - 1) + k) * S->tcp;
+        S->tsim += tau;
+        if (k != 1) {
+            rc = copy_replica(S, 0, k - 1);
+            if (rc) return rc;
+        }
+        o->M = S->par_M; o->k = k; o->to_state = S->st_host->to_state; o->tau_steps = tau; o->tau = (double)tau * S->dt;
+        S->omega = S->st_host->to_state;
+        S->phase = PH_IDLE;
+        HIPCHK(S, hipStreamSynchronize(S->stream));
+        return GPR_OK;
+    }
+    return GPR_BUDGET;
+}
+
+extern "C" gpr_status gpr_advance(gpr_system *S, int64_t nsteps, int64_t *first_exit_check)
+{
+    if (!S) return fail(nullptr, GPR_EINVAL, "NULL system");
+    if (nsteps < 0) return fail(S, GPR_EINVAL, "nsteps < 0");
+    HIPCHK(S, hipMemsetAsync(S->fec, 0, sizeof(long long) * S->R, S->stream));
+    long long t = 0;
+    while (t < nsteps) {
+        const long long k = std::min<long long>(S->tcd - t % S->tcd, nsteps - t);
+        const bool at_check = (t + k) % S->tcd == 0;
+        gpr_status rc = run_steps(S, S->R, k, t, true, at_check);
+        if (rc) return rc;
+        S->nsamp += count_samples(t, t + k, S->t_gr);
+        t += k;
+        if (at_check) {
+            rc = check(S, CHK_ADVANCE, S->R, (int)(t / S->tcd));
+            if (rc) return rc;
+        }
+    }
+    std::vector<long long> f(S->R);
+    HIPCHK(S, hipMemcpyAsync(f.data(), S->fec, sizeof(long long) * S->R, hipMemcpyDeviceToHost, S->stream));
+    int err[4];
+    HIPCHK(S, hipMemcpyAsync(err, S->d.err, sizeof err, hipMemcpyDeviceToHost, S->stream));
+    HIPCHK(S, hipStreamSynchronize(S->stream));
+    if (err[ERR_UNSTABLE]) return fail(S, GPR_EUNSTABLE, "non-finite or overflowing state");
+    if (err[ERR_LIST]) return fail(S, GPR_EDEVICE, "pair-list capacity exceeded");
+    if (first_exit_check) for (int r = 0; r < S->R; ++r) first_exit_check[r] = f[r];
+    return GPR_OK;
+}
+
+// ------------------------------------------------------------------ building blocks
+template <class T>
+static hipError_t tmp_alloc(std::vector<void *> &v, T **p, size_t count)
+{
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+    if (e == hipSuccess) { v.push_back(q); *p = (T *)q; }
+    return e;
+}
+
+struct TmpBufs {
+    std::vector<void *> v;
+    ~TmpBufs() { for (void *p : v) hipFree(p); }
+};
+
+#define TMPCHK(call)                                                                                \
+    do {                                                                                            \
+        hipError_t e_ = (call);                                                                     \
+        if (e_ != hipSuccess) return fail(nullptr, GPR_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+extern "C" gpr_status gpr_philox_noise(uint64_t seed, int32_t replica, int64_t step, int32_t stream, int32_t n_atoms,
+                                       uint32_t *out_words, float *out_gauss)
+{
+    if (n_atoms < 0 || stream < 0 || stream > 255) return fail(nullptr, GPR_EINVAL, "bad arguments");
+    if (n_atoms == 0) return GPR_OK;
+    TmpBufs t;
+    uint32_t *w = nullptr;
+    float *g = nullptr;
+    TMPCHK(tmp_alloc(t.v, &w, 4 * (size_t)n_atoms));
+    TMPCHK(tmp_alloc(t.v, &g, 3 * (size_t)n_atoms));
+    hipLaunchKernelGGL(k_noise_test, dim3((n_atoms + 255) / 256), dim3(256), 0, 0, (uint32_t)seed,
+                       (uint32_t)(seed >> 32), replica, (long long)step, stream, n_atoms, w, g);
+    TMPCHK(hipGetLastError());
+    if (out_words) TMPCHK(hipMemcpy(out_words, w, 16 * (size_t)n_atoms, hipMemcpyDeviceToHost));
+    if (out_gauss) TMPCHK(hipMemcpy(out_gauss, g, 12 * (size_t)n_atoms, hipMemcpyDeviceToHost));
+    TMPCHK(hipDeviceSynchronize());
+    return GPR_OK;
+}
+
+extern "C" gpr_status gpr_fv_plan(uint64_t seed, int64_t step, int32_t R, const uint8_t *exited, int32_t *donor)
+{
+    if (R < 1 || !exited || !donor) return fail(nullptr, GPR_EINVAL, "bad arguments");
+    TmpBufs t;
+    uint8_t *ex = nullptr;
+    int *dn = nullptr, *sv = nullptr;
+    TMPCHK(tmp_alloc(t.v, &ex, R));
+    TMPCHK(tmp_alloc(t.v, &dn, R));
+    TMPCHK(tmp_alloc(t.v, &sv, R));
+    TMPCHK(hipMemcpy(ex, exited, R, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_fvplan_test, dim3(1), dim3(64), 0, 0, (uint32_t)seed, (uint32_t)(seed >> 32), (long long)step, R, ex, dn, sv);
+    TMPCHK(hipGetLastError());
+    TMPCHK(hipMemcpy(donor, dn, sizeof(int) * R, hipMemcpyDeviceToHost));
+    return GPR_OK;
+}
+
+extern "C" gpr_status gpr_rhat(int32_t nw, int32_t n_obs, int64_t n, const double *S1, const double *S2, double *rhat)
+{
+    if (nw < 1 || n_obs < 0 || n_obs > 64 || n < 1 || (n_obs && (!S1 || !S2 || !rhat)))
+        return fail(nullptr, GPR_EINVAL, "bad arguments");
+    if (n_obs == 0) return GPR_OK;
+    TmpBufs t;
+    double *a = nullptr, *b = nullptr, *o = nullptr;
+    const size_t cnt = (size_t)nw * n_obs;
+    TMPCHK(tmp_alloc(t.v, &a, cnt));
+    TMPCHK(tmp_alloc(t.v, &b, cnt));
+    TMPCHK(tmp_alloc(t.v, &o, n_obs));
+    TMPCHK(hipMemcpy(a, S1, cnt * 8, hipMemcpyHostToDevice));
+    TMPCHK(hipMemcpy(b, S2, cnt * 8, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_rhat_test, dim3(1), dim3(64), 0, 0, nw, n_obs, (long long)n, a, b, o);
+    TMPCHK(hipGetLastError());
+    TMPCHK(hipMemcpy(rhat, o, 8 * (size_t)n_obs, hipMemcpyDeviceToHost));
+    return GPR_OK;
+}
+
+extern "C" gpr_status gpr_exit_vote(int32_t R, const int64_t *fec, int64_t t_check, int64_t *M, int32_t *k, int64_t *tau)
+{
+    if (R < 1 || !fec || !M || !k || !tau) return fail(nullptr, GPR_EINVAL, "bad arguments");
+    TmpBufs t;
+    long long *f = nullptr, *o = nullptr;
+    TMPCHK(tmp_alloc(t.v, &f, R));
+    TMPCHK(tmp_alloc(t.v, &o, 3));
+    TMPCHK(hipMemcpy(f, fec, 8 * (size_t)R, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_vote_test, dim3(1), dim3(64), 0, 0, R, f, (long long)t_check, o);
+    TMPCHK(hipGetLastError());
+    long long h[3];
+    TMPCHK(hipMemcpy(h, o, sizeof h, hipMemcpyDeviceToHost));
+    if (h[0] == 0) return GPR_BUDGET;
+    *M = h[0];
+    *k = (int32_t)h[1];
+    *tau = h[2];
+    return GPR_OK;
+}

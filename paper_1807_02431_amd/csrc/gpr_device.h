@@ -1,0 +1,253 @@
+// gpr_device.h -- device-side data layout and arithmetic of the MI355X Gen.ParRep hot path.
+//
+// Layout in HBM (per system; R replicas, n atoms padded to np = multiple of 64):
+//   x, v      float  [R][3][np]   SoA per replica (coalesced per coordinate)
+//   F         int64  [R][3][np]   forces in 64-bit fixed point, 2^-32 kJ/mol/nm per unit
+//   xb        float  [R][3][np]   positions at the last pair-list build (displacement guard)
+//   nbl       uint16 [R][K][np*P] pair lists, slot-major: entry k of sub-list (i, q) at
+//                                 k*np*P + i*P + q, so the P lanes of consecutive atoms read
+//                                 consecutive halfwords
+//   nbc       uint16 [R][np*P]    sub-list lengths
+//   acc       double [R][MAX_OBS][2]  observable sums S1, S2 (Eq. 2-3)
+// Per-atom parameters (shared by all replicas): prm = (sigma/2, 2 sqrt(eps), q sqrt(f), 1/m).
+//
+// Determinism: every force contribution that is scattered (bonded terms) is rounded to the
+// 2^-32 fixed-point grid and added as an integer; the nonbonded force of atom i is an FP32
+// sum over P sub-lists, sub-list q holding the partners j = q (mod P) in ascending order,
+// and pairs beyond the cutoff add an exact zero, so the sum does not depend on the list
+// contents beyond the in-cutoff pairs, nor on launch shape or list rebuild times.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gpr {
+
+constexpr int P = 4;            // lanes per atom in the pair loop (sub-lists by j mod P)
+constexpr int MAX_OBS = 8;
+constexpr int CHMAX = 4;        // atoms per thread in the integrator mapping
+constexpr int BLK = 32;         // atoms per bounding sphere in the pair search
+constexpr double FIX = 4294967296.0;          // 2^32
+constexpr double FIX_INV = 2.3283064365386963e-10;  // 2^-32
+constexpr float FMAX_FIX = 1.0e9f;             // |F| beyond this counts as unstable
+
+enum { KIND_TOY = 1, KIND_MOL = 2 };
+enum { ST_SIGN_X = 1, ST_BOXES = 2, ST_COM = 3 };
+enum { OB_COORD = 1, OB_POT = 2, OB_KIN = 3, OB_DIH = 4, OB_COMD = 5, OB_RMSV = 6 };
+enum { STREAM_NOISE = 0, STREAM_INIT = 1, STREAM_BRANCH = 2 };
+enum { ERR_UNSTABLE = 0, ERR_LIST = 1, ERR_BARRIER = 2 };
+
+struct ObsDesc {
+    int kind;
+    int atoms[4];
+    int ga_off, ga_n, gb_off, gb_n;
+    double ma, mb;   // total masses of the groups
+};
+
+struct StateDesc {
+    int kind;
+    int atoms[8];
+    int nbox;
+    double box[8][4];
+    int g_off, g_n;
+    double gm;       // total mass of the group
+    double center[3];
+    double radius;
+};
+
+// bonded terms, each type sorted by its smallest atom index; *_start[a] is the first term
+// whose smallest atom is >= a (length n+1); *_span the largest index spread of a term
+struct Topo {
+    int nb; const int2 *b_ij; const float2 *b_p; const int *b_start; int b_span;            // (r0, k)
+    int na; const int4 *a_ijk; const float2 *a_p; const int *a_start; int a_span;           // (theta0, k)
+    int nt; const int4 *t_ijkl; const float4 *t_p; const int *t_start; int t_span;          // (k, phi0, n)
+    int nr; const int *r_i; const float4 *r_p; const int *r_start;                          // (ref xyz, k)
+    int n14; const int2 *p_ij; const float4 *p_p; const int *p_start; int p_span;           // (s, 4e*sc, qq*sc)
+};
+
+struct Dev {
+    int kind, n, np, R;
+    const float4 *prm;
+    const float *sd;                       // sqrt((1 - c1^2) kT / m)
+    const float *mass;
+    const unsigned long long *excl;        // bit (j - i + 32) set: pair excluded or 1-4
+    float *x, *v, *xb;
+    long long *F;
+    long long *E;                          // [R] potential energy, fixed point
+    unsigned short *nbl, *nbc;
+    int K;                                 // capacity of one sub-list
+    int *guard;                            // [2][R] displacement guard flags by step parity
+    int *need_build;                       // [R]
+    int *err;                              // [4] error flags
+    double *acc;                           // [R][MAX_OBS][2]
+    double *shift;                         // [MAX_OBS]
+    int *state;                            // [R]
+    const int *groups;
+    int nobs;
+    int need_energy;                       // an observable is the potential energy
+    ObsDesc obs[MAX_OBS];
+    StateDesc st;
+    Topo tp;
+    float h, c1, rc2, rl, rl2, krf, crf, half_skin2;
+    int cutoff_on, period;
+    uint32_t key0, key1;
+    int t_gr;
+};
+
+// ------------------------------------------------------------------ Philox4x32-10
+// Salmon, Moraes, Dror, Shaw (SC'11): ten rounds; each multiplies words 0 and 2 by fixed
+// 32-bit constants, crosses the high halves with words 1 and 3 and the round key, and
+// bumps the key by the Weyl increments between rounds.
+__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int rnd = 0; rnd < 10; ++rnd) {
+        const uint32_t lo0 = 0xD2511F53u * c.x;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+__device__ __forceinline__ uint4 philox_ctr(uint32_t atom, long long step, uint32_t replica, uint32_t stream,
+                                            uint32_t k0, uint32_t k1)
+{
+    const unsigned long long us = (unsigned long long)step;
+    return philox10(make_uint4(atom, (uint32_t)us, replica, (stream << 24) | ((uint32_t)(us >> 32) & 0xFFFFFFu)),
+                    k0, k1);
+}
+
+// odd multiple of 2^-24 in (0, 1): exact in FP32
+__device__ __forceinline__ float unit_open(uint32_t w)
+{
+    return (float)(2u * (w >> 9) + 1u) * 5.9604644775390625e-08f;
+}
+
+// Box-Muller: (z0, z1) from (u0, u1), z2 from (u2, u3)
+__device__ __forceinline__ float3 gauss3(uint4 w)
+{
+    const float ra = sqrtf(-2.0f * logf(unit_open(w.x)));
+    const float rb = sqrtf(-2.0f * logf(unit_open(w.z)));
+    float s1, c1;
+    sincospif(2.0f * unit_open(w.y), &s1, &c1);
+    const float c3 = cospif(2.0f * unit_open(w.w));
+    return make_float3(ra * c1, ra * s1, rb * c3);
+}
+
+// ------------------------------------------------------------------ fixed point
+__device__ __forceinline__ long long fix_f(float f) { return __double2ll_rn((double)f * FIX); }
+__device__ __forceinline__ long long fix_d(double d) { return __double2ll_rn(d * FIX); }
+__device__ __forceinline__ float unfix_f(long long a) { return (float)((double)a * FIX_INV); }
+__device__ __forceinline__ double unfix_d(long long a) { return (double)a * FIX_INV; }
+
+__device__ __forceinline__ void lds_add(long long *p, long long v)
+{
+    atomicAdd((unsigned long long *)p, (unsigned long long)v);
+}
+
+__device__ __forceinline__ bool bad_force(float f) { return !(fabsf(f) < FMAX_FIX); }
+
+// ------------------------------------------------------------------ bonded terms (FP32)
+// Each returns the energy and writes the force on every atom of the term.
+
+// bond 1/2 k (r - r0)^2
+__device__ __forceinline__ float term_bond(float3 pi, float3 pj, float2 p, float3 &fi)
+{
+    const float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+    const float r = sqrtf(dx * dx + dy * dy + dz * dz);
+    const float dr = r - p.x;
+    const float g = p.y * dr / r;   // force on i along (pj - pi)
+    fi = make_float3(g * dx, g * dy, g * dz);
+    return 0.5f * p.y * dr * dr;
+}
+
+// angle 1/2 k (theta - theta0)^2 with theta = atan2(|u x w|, u . w), vertex j
+__device__ __forceinline__ float term_angle(float3 pi, float3 pj, float3 pk, float2 p, float3 &fi, float3 &fk)
+{
+    const float ux = pi.x - pj.x, uy = pi.y - pj.y, uz = pi.z - pj.z;
+    const float wx = pk.x - pj.x, wy = pk.y - pj.y, wz = pk.z - pj.z;
+    const float cx = uy * wz - uz * wy, cy = uz * wx - ux * wz, cz = ux * wy - uy * wx;
+    const float sn = sqrtf(cx * cx + cy * cy + cz * cz);
+    const float cs = ux * wx + uy * wy + uz * wz;
+    const float th = atan2f(sn, cs);
+    const float dth = th - p.x;
+    const float lu2 = ux * ux + uy * uy + uz * uz, lw2 = wx * wx + wy * wy + wz * wz;
+    // d theta / d p_i = (cos(theta) u/|u|^2 - w/(|u||w|)) / sin(theta); sin(theta) |u||w| = sn
+    const float g = -p.y * dth;
+    const float a = g / sn;                         // g / (|u||w| sin theta)
+    const float cu = cs / lu2, cw = cs / lw2;
+    fi = make_float3(a * (cu * ux - wx), a * (cu * uy - wy), a * (cu * uz - wz));
+    fk = make_float3(a * (cw * wx - ux), a * (cw * wy - uy), a * (cw * wz - uz));
+    return 0.5f * p.y * dth * dth;
+}
+
+// torsion k (1 + cos(n phi - phi0)); phi from b1 = pj - pi, b2 = pk - pj, b3 = pl - pk:
+// phi = atan2(|b2| b1 . (b2 x b3), (b1 x b2) . (b2 x b3)) (IUPAC, trans = pi).  Gradient
+// (Bekker; Blondel and Karplus 1996): dphi/dp_i = -|b2|/|n1|^2 n1, dphi/dp_l = |b2|/|n2|^2 n2,
+// the middle atoms take the remainder weighted by the projections of b1 and b3 on b2
+// (p12 = b1.b2/|b2|^2, p32 = b3.b2/|b2|^2), so that net force and torque vanish.
+__device__ __forceinline__ float term_torsion(float3 pi, float3 pj, float3 pk, float3 pl, float4 p,
+                                              float3 &fi, float3 &fj, float3 &fk, float3 &fl)
+{
+    const float b1x = pj.x - pi.x, b1y = pj.y - pi.y, b1z = pj.z - pi.z;
+    const float b2x = pk.x - pj.x, b2y = pk.y - pj.y, b2z = pk.z - pj.z;
+    const float b3x = pl.x - pk.x, b3y = pl.y - pk.y, b3z = pl.z - pk.z;
+    const float n1x = b1y * b2z - b1z * b2y, n1y = b1z * b2x - b1x * b2z, n1z = b1x * b2y - b1y * b2x;
+    const float n2x = b2y * b3z - b2z * b3y, n2y = b2z * b3x - b2x * b3z, n2z = b2x * b3y - b2y * b3x;
+    const float lb2sq = b2x * b2x + b2y * b2y + b2z * b2z;
+    const float lb2 = sqrtf(lb2sq);
+    const float xx = n1x * n2x + n1y * n2y + n1z * n2z;
+    const float yy = lb2 * (b1x * n2x + b1y * n2y + b1z * n2z);
+    const float phi = atan2f(yy, xx);
+    const float arg = p.z * phi - p.y;
+    float sa, ca;
+    sincosf(arg, &sa, &ca);
+    const float dUdphi = -p.x * p.z * sa;
+    const float n1sq = n1x * n1x + n1y * n1y + n1z * n1z;
+    const float n2sq = n2x * n2x + n2y * n2y + n2z * n2z;
+    const float ai = dUdphi * lb2 / n1sq;     // F_i = -dU/dphi dphi/dp_i = +dU/dphi |b2|/|n1|^2 n1
+    const float al = -dUdphi * lb2 / n2sq;    // F_l = -dU/dphi |b2|/|n2|^2 n2
+    fi = make_float3(ai * n1x, ai * n1y, ai * n1z);
+    fl = make_float3(al * n2x, al * n2y, al * n2z);
+    const float p12 = (b1x * b2x + b1y * b2y + b1z * b2z) / lb2sq;
+    const float p32 = (b3x * b2x + b3y * b2y + b3z * b2z) / lb2sq;
+    // F_j = -(1 + p12) F_i + p32 F_l ; F_k = p12 F_i - (1 + p32) F_l
+    const float aj = -(1.0f + p12), ak = -(1.0f + p32);
+    fj = make_float3(aj * fi.x + p32 * fl.x, aj * fi.y + p32 * fl.y, aj * fi.z + p32 * fl.z);
+    fk = make_float3(p12 * fi.x + ak * fl.x, p12 * fi.y + ak * fl.y, p12 * fi.z + ak * fl.z);
+    return p.x * (1.0f + ca);
+}
+
+// 1-4 pair: scale (LJ + vacuum Coulomb), parameters pre-multiplied by the scale
+__device__ __forceinline__ float term_pair14(float3 pi, float3 pj, float4 p, float3 &fi)
+{
+    const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    const float ri = 1.0f / sqrtf(r2);
+    const float r2i = ri * ri;
+    const float s2 = p.x * p.x * r2i;
+    const float s6 = s2 * s2 * s2;
+    const float u = p.y * (s6 * s6 - s6) + p.z * ri;
+    const float fs = p.y * r2i * (12.0f * s6 * s6 - 6.0f * s6) + p.z * ri * r2i;
+    fi = make_float3(fs * dx, fs * dy, fs * dz);
+    return u;
+}
+
+// ------------------------------------------------------------------ FP64 geometry for states and observables
+__device__ __forceinline__ double dihedral_d(double3 a, double3 b, double3 c, double3 d)
+{
+    const double b1x = b.x - a.x, b1y = b.y - a.y, b1z = b.z - a.z;
+    const double b2x = c.x - b.x, b2y = c.y - b.y, b2z = c.z - b.z;
+    const double b3x = d.x - c.x, b3y = d.y - c.y, b3z = d.z - c.z;
+    const double n1x = b1y * b2z - b1z * b2y, n1y = b1z * b2x - b1x * b2z, n1z = b1x * b2y - b1y * b2x;
+    const double n2x = b2y * b3z - b2z * b3y, n2y = b2z * b3x - b2x * b3z, n2z = b2x * b3y - b2y * b3x;
+    const double lb2 = sqrt(b2x * b2x + b2y * b2y + b2z * b2z);
+    const double xx = n1x * n2x + n1y * n2y + n1z * n2z;
+    const double yy = lb2 * (b1x * n2x + b1y * n2y + b1z * n2z);
+    return atan2(yy, xx);
+}
+
+} // namespace gpr

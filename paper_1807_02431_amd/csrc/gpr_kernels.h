@@ -1,0 +1,37 @@
+// gpr_kernels.h -- kernel entry points of the Gen.ParRep hot path (launched by gpr_api.hip).
+#pragma once
+#include "gpr_device.h"
+
+namespace gpr {
+
+enum { CHK_STATE = 0, CHK_DEPHASE = 1, CHK_PARALLEL = 2, CHK_ADVANCE = 3 };
+
+// per-check status word read back by the host
+struct Status {
+    int mode;
+    int ref_exited;     // dephasing: the reference walker left Omega
+    int n_exited;       // dephasing: workers that left Omega at this check
+    int n_surv;         // dephasing: surviving workers
+    int k;              // parallel step: 1-based index of the first exiting replica, 0 if none
+    int to_state;       // state of replica 0 (or of replica k-1 in the parallel step)
+    int err[4];
+    double rhat[MAX_OBS];
+};
+
+__global__ void k_integrate(Dev S, long long s, int r_off, int energy);
+__global__ void k_bonded(Dev S, int r_off, int energy);
+__global__ void k_nonbonded(Dev S, long long s, int r_off, int energy, int apply_b, int force_build);
+__global__ void k_obs(Dev S, int r_off, int mode, double *out);
+__global__ void k_state(Dev S, int r_off);
+__global__ void k_persist(Dev S, long long s0, int nsteps, int t0, int sample, int state_end);
+__global__ void k_check(Dev S, int mode, long long s, int omega, int nrep, long long nsamp, int check_index,
+                        Status *st, int *donor, int *surv, long long *fec);
+__global__ void k_clone(Dev S, const int *donor, int acc_mode);
+__global__ void k_init_vel(Dev S, float kT);
+__global__ void k_noise_test(uint32_t k0, uint32_t k1, int replica, long long step, int stream, int n,
+                             uint32_t *words, float *gauss);
+__global__ void k_fvplan_test(uint32_t k0, uint32_t k1, long long s, int R, const uint8_t *exited, int *donor, int *surv);
+__global__ void k_rhat_test(int nw, int nobs, long long n, const double *S1, const double *S2, double *out);
+__global__ void k_vote_test(int R, const long long *fec, long long t_check, long long *out);
+
+} // namespace gpr

@@ -1,0 +1,946 @@
+// gpr_kernels.hip -- gfx950 kernels of the Gen.ParRep hot path.
+//
+// Two stepping paths share every arithmetic routine, so they give bit-identical results:
+//   plain      : per step, k_integrate (B A O A of Eq. 1's BAOAB discretisation),
+//                k_bonded, k_nonbonded (pair forces, the closing B kick, pair-list rebuild
+//                when due); observables and state tests as separate launches;
+//   persistent : k_persist advances one replica per workgroup for a whole check period,
+//                with its positions and parameters resident in LDS and its velocities and
+//                forces in registers.
+// Gen.ParRep bookkeeping (Sec. 2.4.1 branching and Gelman-Rubin, Sec. 2.4.2 exit vote)
+// runs in k_check / k_clone once per check.
+#include "gpr_kernels.h"
+
+namespace gpr {
+
+// ------------------------------------------------------------------ small helpers
+__device__ __forceinline__ float kick(float v, float F, float h, float im) { return v + (h * F) * im; }
+
+__device__ __forceinline__ long long wave_sum_ll(long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// the P = 4 lanes of one atom are consecutive: (s0 + s1) + (s2 + s3) in a fixed order
+__device__ __forceinline__ float quad_sum(float v)
+{
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    return v;
+}
+
+struct PosLDS {
+    const float4 *xs;
+    __device__ float3 operator()(int a) const { const float4 p = xs[a]; return make_float3(p.x, p.y, p.z); }
+};
+struct PosGlob {
+    const float *x;
+    int np;
+    __device__ float3 operator()(int a) const { return make_float3(x[a], x[np + a], x[2 * np + a]); }
+};
+
+__device__ __forceinline__ float3 neg3(float3 f) { return make_float3(-f.x, -f.y, -f.z); }
+
+// ------------------------------------------------------------------ bonded terms of an atom range
+// Adds, for every term touching atoms [a0, a1), the fixed-point forces on the atoms of the
+// range to fa[3][len] (LDS, index a - a0); the energy of a term is counted by the range
+// holding its smallest atom.
+template <class Pos>
+__device__ void bonded_range(const Dev &S, const Pos &pos, int a0, int a1, long long *fa, int len,
+                             long long *e_acc, int tid, int nthr)
+{
+    const Topo &T = S.tp;
+    auto add = [&](int a, float3 f) {
+        if (a >= a0 && a < a1) {
+            lds_add(&fa[a - a0], fix_f(f.x));
+            lds_add(&fa[len + a - a0], fix_f(f.y));
+            lds_add(&fa[2 * len + a - a0], fix_f(f.z));
+        }
+    };
+    long long e = 0;
+    if (T.nb) {
+        const int lo = T.b_start[max(0, a0 - T.b_span)], hi = T.b_start[a1];
+        for (int t = lo + tid; t < hi; t += nthr) {
+            const int2 ij = T.b_ij[t];
+            float3 fi;
+            const float u = term_bond(pos(ij.x), pos(ij.y), T.b_p[t], fi);
+            add(ij.x, fi);
+            add(ij.y, neg3(fi));
+            const int mn = min(ij.x, ij.y);
+            if (e_acc && mn >= a0) e += fix_f(u);
+        }
+    }
+    if (T.na) {
+        const int lo = T.a_start[max(0, a0 - T.a_span)], hi = T.a_start[a1];
+        for (int t = lo + tid; t < hi; t += nthr) {
+            const int4 q = T.a_ijk[t];
+            float3 fi, fk;
+            const float u = term_angle(pos(q.x), pos(q.y), pos(q.z), T.a_p[t], fi, fk);
+            add(q.x, fi);
+            add(q.z, fk);
+            add(q.y, make_float3(-fi.x - fk.x, -fi.y - fk.y, -fi.z - fk.z));
+            const int mn = min(q.x, min(q.y, q.z));
+            if (e_acc && mn >= a0) e += fix_f(u);
+        }
+    }
+    if (T.nt) {
+        const int lo = T.t_start[max(0, a0 - T.t_span)], hi = T.t_start[a1];
+        for (int t = lo + tid; t < hi; t += nthr) {
+            const int4 q = T.t_ijkl[t];
+            float3 fi, fj, fk, fl;
+            const float u = term_torsion(pos(q.x), pos(q.y), pos(q.z), pos(q.w), T.t_p[t], fi, fj, fk, fl);
+            add(q.x, fi);
+            add(q.y, fj);
+            add(q.z, fk);
+            add(q.w, fl);
+            const int mn = min(min(q.x, q.y), min(q.z, q.w));
+            if (e_acc && mn >= a0) e += fix_f(u);
+        }
+    }
+    if (T.nr) {
+        const int lo = T.r_start[a0], hi = T.r_start[a1];
+        for (int t = lo + tid; t < hi; t += nthr) {
+            const int a = T.r_i[t];
+            const float4 p = T.r_p[t];
+            const float3 x = pos(a);
+            const float dx = x.x - p.x, dy = x.y - p.y, dz = x.z - p.z;
+            add(a, make_float3(-p.w * dx, -p.w * dy, -p.w * dz));
+            if (e_acc) e += fix_f(0.5f * p.w * (dx * dx + dy * dy + dz * dz));
+        }
+    }
+    if (T.n14) {
+        const int lo = T.p_start[max(0, a0 - T.p_span)], hi = T.p_start[a1];
+        for (int t = lo + tid; t < hi; t += nthr) {
+            const int2 ij = T.p_ij[t];
+            float3 fi;
+            const float u = term_pair14(pos(ij.x), pos(ij.y), T.p_p[t], fi);
+            add(ij.x, fi);
+            add(ij.y, neg3(fi));
+            const int mn = min(ij.x, ij.y);
+            if (e_acc && mn >= a0) e += fix_f(u);
+        }
+    }
+    if (e_acc && e != 0) lds_add(e_acc, e);
+}
+
+// the double well of the toy system, U = (x^2 - 1)^2 + 2 y^2
+__device__ __forceinline__ float toy_force(float x, float y, float &fx, float &fy)
+{
+    const float x2m1 = x * x - 1.0f;
+    fx = -4.0f * x * x2m1;
+    fy = -4.0f * y;
+    return x2m1 * x2m1 + 2.0f * y * y;
+}
+
+// ------------------------------------------------------------------ pair search
+// Bounding spheres of the blocks of BLK consecutive atoms (chain-local, so compact).
+__device__ void block_spheres(const Dev &S, const float4 *xs, float4 *sph, int tid, int nthr)
+{
+    const int nblk = (S.n + BLK - 1) / BLK;
+    for (int b = tid; b < nblk; b += nthr) {
+        const int a0 = b * BLK, a1 = min(S.n, a0 + BLK);
+        float cx = 0.f, cy = 0.f, cz = 0.f;
+        for (int a = a0; a < a1; ++a) { cx += xs[a].x; cy += xs[a].y; cz += xs[a].z; }
+        const float inv = 1.0f / (float)(a1 - a0);
+        cx *= inv; cy *= inv; cz *= inv;
+        float r2 = 0.f;
+        for (int a = a0; a < a1; ++a) {
+            const float dx = xs[a].x - cx, dy = xs[a].y - cy, dz = xs[a].z - cz;
+            r2 = fmaxf(r2, dx * dx + dy * dy + dz * dz);
+        }
+        sph[b] = make_float4(cx, cy, cz, sqrtf(r2) * 1.0001f + 1e-6f);
+    }
+}
+
+// Sub-list (i, q): partners j = q (mod P), j != i, not excluded, |x_i - x_j| < r_list, in
+// ascending order.  allpairs: no distance test (vacuum systems without cutoff).
+__device__ void build_lane(const Dev &S, int r, int i, int q, const float4 *xs, const float4 *sph, bool allpairs)
+{
+    const size_t stride = (size_t)S.np * P;
+    unsigned short *L = S.nbl + (size_t)r * S.K * stride + (size_t)i * P + q;
+    const float4 pi = xs[i];
+    const unsigned long long ex = S.excl[i];
+    const int nblk = (S.n + BLK - 1) / BLK;
+    int cnt = 0;
+    bool over = false;
+    for (int b = 0; b < nblk; ++b) {
+        if (!allpairs) {
+            const float4 c = sph[b];
+            const float dx = pi.x - c.x, dy = pi.y - c.y, dz = pi.z - c.z;
+            const float lim = S.rl + c.w;
+            if (dx * dx + dy * dy + dz * dz >= lim * lim) continue;
+        }
+        const int jend = min(S.n, (b + 1) * BLK);
+        for (int j = b * BLK + q; j < jend; j += P) {
+            if (j == i) continue;
+            const int off = j - i;
+            if (off >= -32 && off < 32 && ((ex >> (off + 32)) & 1ull)) continue;
+            if (!allpairs) {
+                const float4 pj = xs[j];
+                const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+                if (dx * dx + dy * dy + dz * dz >= S.rl2) continue;
+            }
+            if (cnt < S.K) L[(size_t)cnt * stride] = (unsigned short)j;
+            else over = true;
+            ++cnt;
+        }
+    }
+    S.nbc[(size_t)r * stride + (size_t)i * P + q] = (unsigned short)min(cnt, S.K);
+    if (over) atomicOr(&S.err[ERR_LIST], 1);
+}
+
+// ------------------------------------------------------------------ nonbonded partial sum of one lane
+// Lennard-Jones + Coulomb (vacuum when krf = crf = 0 and rc2 = inf; reaction field
+// otherwise) over sub-list (i, q); returns (F_x, F_y, F_z, U/2 summed over the partners).
+__device__ __forceinline__ float4 nb_lane(const Dev &S, int r, int i, int q, const float4 *xs, const float2 *pp,
+                                          bool energy)
+{
+    const size_t stride = (size_t)S.np * P;
+    const unsigned short *L = S.nbl + (size_t)r * S.K * stride + (size_t)i * P + q;
+    const int cnt = S.nbc[(size_t)r * stride + (size_t)i * P + q];
+    const float4 pi = xs[i];
+    const float2 ppi = pp[i];
+    const float rc2 = S.rc2, krf2 = 2.0f * S.krf;
+    float fx = 0.f, fy = 0.f, fz = 0.f, e = 0.f;
+    for (int k = 0; k < cnt; ++k) {
+        const int j = L[(size_t)k * stride];
+        const float4 pj = xs[j];
+        const float2 ppj = pp[j];
+        const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const float ri = __builtin_amdgcn_rsqf(r2);
+        const float r2i = ri * ri;
+        const float sg = ppi.x + ppj.x;
+        const float s2 = sg * sg * r2i;
+        const float s6 = s2 * s2 * s2;
+        const float e4 = ppi.y * ppj.y;
+        const float qq = pi.w * pj.w;
+        float fs = e4 * r2i * (12.0f * s6 * s6 - 6.0f * s6) + qq * (ri * r2i - krf2);
+        const bool in = r2 < rc2;
+        fs = in ? fs : 0.0f;
+        fx += fs * dx;
+        fy += fs * dy;
+        fz += fs * dz;
+        if (energy) {
+            const float u = e4 * (s6 * s6 - s6) + qq * (ri + S.krf * r2 - S.crf);
+            e += in ? 0.5f * u : 0.0f;
+        }
+    }
+    return make_float4(fx, fy, fz, e);
+}
+
+// ------------------------------------------------------------------ one B A O A for one atom
+__device__ __forceinline__ void integrate_baoa(const Dev &S, int a, int r, long long s, float3 &x, float3 &v,
+                                               float3 F, float im, float sd)
+{
+    const float h = S.h, c1 = S.c1;
+    v.x = kick(v.x, F.x, h, im);
+    v.y = kick(v.y, F.y, h, im);
+    v.z = kick(v.z, F.z, h, im);
+    x.x = x.x + h * v.x;
+    x.y = x.y + h * v.y;
+    x.z = x.z + h * v.z;
+    const float3 g = gauss3(philox_ctr((uint32_t)a, s, (uint32_t)r, STREAM_NOISE, S.key0, S.key1));
+    v.x = c1 * v.x + sd * g.x;
+    v.y = c1 * v.y + sd * g.y;
+    if (S.kind != KIND_TOY) v.z = c1 * v.z + sd * g.z;
+    x.x = x.x + h * v.x;
+    x.y = x.y + h * v.y;
+    x.z = x.z + h * v.z;
+}
+
+__device__ __forceinline__ bool finite3(float3 a) { return isfinite(a.x) && isfinite(a.y) && isfinite(a.z); }
+
+// ------------------------------------------------------------------ states and observables (FP64)
+// Workgroup-collective.  Sums over atoms are taken in 2^-32 fixed point so that they do
+// not depend on the launch shape.  red: LDS int64 scratch [MAX_OBS * 8 + 8].
+__device__ void group_sum_wg(const Dev &S, const float4 *xs, const float *vg, int off, int cnt, int what,
+                             long long *dst, int tid, int nthr)
+{
+    // what: 0 -> sum m x (3 slots), 1 -> sum |v|^2 (1 slot)
+    for (int base = 0; base < cnt; base += nthr) {
+        const int k = base + tid;
+        long long s0 = 0, s1 = 0, s2 = 0;
+        if (k < cnt) {
+            const int a = S.groups[off + k];
+            if (what == 0) {
+                const double m = (double)S.mass[a];
+                s0 = fix_d(m * (double)xs[a].x);
+                s1 = fix_d(m * (double)xs[a].y);
+                s2 = fix_d(m * (double)xs[a].z);
+            } else {
+                const double vx = vg[a], vy = vg[S.np + a], vz = vg[2 * S.np + a];
+                s0 = fix_d(vx * vx + vy * vy + vz * vz);
+            }
+        }
+        s0 = wave_sum_ll(s0);
+        if (what == 0) { s1 = wave_sum_ll(s1); s2 = wave_sum_ll(s2); }
+        if ((tid & 63) == 0) {
+            lds_add(&dst[0], s0);
+            if (what == 0) { lds_add(&dst[1], s1); lds_add(&dst[2], s2); }
+        }
+    }
+}
+
+__device__ __forceinline__ double3 xs_d(const float4 *xs, int a)
+{
+    return make_double3((double)xs[a].x, (double)xs[a].y, (double)xs[a].z);
+}
+
+__device__ int state_wg(const Dev &S, const float4 *xs, long long *red, int *sbuf, int tid, int nthr)
+{
+    const StateDesc &st = S.st;
+    if (st.kind == ST_SIGN_X) return xs[st.atoms[0]].x >= 0.0f ? 1 : 0;
+    if (st.kind == ST_BOXES) {
+        if (tid == 0) {
+            const double phi = dihedral_d(xs_d(xs, st.atoms[0]), xs_d(xs, st.atoms[1]), xs_d(xs, st.atoms[2]), xs_d(xs, st.atoms[3]));
+            const double psi = dihedral_d(xs_d(xs, st.atoms[4]), xs_d(xs, st.atoms[5]), xs_d(xs, st.atoms[6]), xs_d(xs, st.atoms[7]));
+            int id = -1;
+            for (int b = 0; b < st.nbox; ++b)
+                if (st.box[b][0] < phi && phi <= st.box[b][1] && st.box[b][2] < psi && psi <= st.box[b][3]) { id = b; break; }
+            *sbuf = id;
+        }
+        __syncthreads();
+        const int id = *sbuf;
+        __syncthreads();
+        return id;
+    }
+    // centre of mass within a sphere
+    if (tid < 3) red[tid] = 0;
+    __syncthreads();
+    group_sum_wg(S, xs, nullptr, st.g_off, st.g_n, 0, red, tid, nthr);
+    __syncthreads();
+    if (tid == 0) {
+        const double cx = unfix_d(red[0]) / st.gm, cy = unfix_d(red[1]) / st.gm, cz = unfix_d(red[2]) / st.gm;
+        const double dx = cx - st.center[0], dy = cy - st.center[1], dz = cz - st.center[2];
+        *sbuf = sqrt(dx * dx + dy * dy + dz * dz) < st.radius ? 1 : 0;
+    }
+    __syncthreads();
+    const int id = *sbuf;
+    __syncthreads();
+    return id;
+}
+
+// observable values into out[MAX_OBS] (LDS), valid after return
+__device__ void observables_wg(const Dev &S, const float4 *xs, const float *vg, double U, long long *red,
+                               double *out, int tid, int nthr)
+{
+    if (tid < MAX_OBS * 8) red[tid] = 0;
+    __syncthreads();
+    for (int j = 0; j < S.nobs; ++j) {
+        const ObsDesc &o = S.obs[j];
+        long long *dst = red + 8 * j;
+        if (o.kind == OB_KIN) {
+            for (int base = 0; base < S.n; base += nthr) {
+                const int a = base + tid;
+                long long s = 0;
+                if (a < S.n) {
+                    const double vx = vg[a], vy = vg[S.np + a], vz = vg[2 * S.np + a];
+                    s = fix_d(0.5 * (double)S.mass[a] * (vx * vx + vy * vy + vz * vz));
+                }
+                s = wave_sum_ll(s);
+                if ((tid & 63) == 0) lds_add(dst, s);
+            }
+        } else if (o.kind == OB_COMD) {
+            group_sum_wg(S, xs, vg, o.ga_off, o.ga_n, 0, dst, tid, nthr);
+            group_sum_wg(S, xs, vg, o.gb_off, o.gb_n, 0, dst + 3, tid, nthr);
+        } else if (o.kind == OB_RMSV) {
+            group_sum_wg(S, xs, vg, o.ga_off, o.ga_n, 1, dst, tid, nthr);
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int j = 0; j < S.nobs; ++j) {
+            const ObsDesc &o = S.obs[j];
+            const long long *src = red + 8 * j;
+            double val = 0.0;
+            switch (o.kind) {
+            case OB_COORD: {
+                const float4 p = xs[o.atoms[0]];
+                val = o.atoms[1] == 0 ? (double)p.x : (o.atoms[1] == 1 ? (double)p.y : (double)p.z);
+                break;
+            }
+            case OB_POT: val = U; break;
+            case OB_KIN: val = unfix_d(src[0]); break;
+            case OB_DIH:
+                val = dihedral_d(xs_d(xs, o.atoms[0]), xs_d(xs, o.atoms[1]), xs_d(xs, o.atoms[2]), xs_d(xs, o.atoms[3]));
+                break;
+            case OB_COMD: {
+                const double ax = unfix_d(src[0]) / o.ma, ay = unfix_d(src[1]) / o.ma, az = unfix_d(src[2]) / o.ma;
+                const double bx = unfix_d(src[3]) / o.mb, by = unfix_d(src[4]) / o.mb, bz = unfix_d(src[5]) / o.mb;
+                val = sqrt((ax - bx) * (ax - bx) + (ay - by) * (ay - by) + (az - bz) * (az - bz));
+                break;
+            }
+            case OB_RMSV: val = sqrt(unfix_d(src[0]) / (double)o.ga_n); break;
+            default: break;
+            }
+            out[j] = val;
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void accumulate_obs(const Dev &S, int r, const double *out)
+{
+    double *acc = S.acc + (size_t)r * MAX_OBS * 2;
+    for (int j = 0; j < S.nobs; ++j) {
+        const double xj = out[j] - S.shift[j];
+        acc[2 * j] += xj;
+        const double x2 = xj * xj;
+        acc[2 * j + 1] += x2;
+    }
+}
+
+// stage positions (x, y, z, q sqrt f) and (sigma/2, 2 sqrt eps) of replica r into LDS
+__device__ __forceinline__ void stage_replica(const Dev &S, int r, float4 *xs, float2 *pp, int tid, int nthr)
+{
+    const float *xg = S.x + (size_t)r * 3 * S.np;
+    for (int a = tid; a < S.np; a += nthr) {
+        const float4 pr = S.prm[a];
+        if (a < S.n) xs[a] = make_float4(xg[a], xg[S.np + a], xg[2 * S.np + a], pr.z);
+        else xs[a] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (pp) pp[a] = make_float2(pr.x, pr.y);
+    }
+}
+
+// ================================================================== plain path kernels
+// B A O A for every atom of replicas r_off + blockIdx.y; displacement guard; energy reset.
+__global__ void __launch_bounds__(256) k_integrate(Dev S, long long s, int r_off, int energy)
+{
+    const int r = r_off + blockIdx.y;
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    int *guard = S.guard + (s & 1) * S.R + r;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (energy) S.E[r] = 0;
+        if (S.need_build[r]) { atomicOr(guard, 1); S.need_build[r] = 0; }
+    }
+    if (a >= S.n) return;
+    const size_t b = (size_t)r * 3 * S.np;
+    float3 x = make_float3(S.x[b + a], S.x[b + S.np + a], S.x[b + 2 * S.np + a]);
+    float3 v = make_float3(S.v[b + a], S.v[b + S.np + a], S.v[b + 2 * S.np + a]);
+    const float3 F = make_float3(unfix_f(S.F[b + a]), unfix_f(S.F[b + S.np + a]), unfix_f(S.F[b + 2 * S.np + a]));
+    const float im = S.prm[a].w;
+    integrate_baoa(S, a, r, s, x, v, F, im, S.sd[a]);
+    S.x[b + a] = x.x; S.x[b + S.np + a] = x.y; S.x[b + 2 * S.np + a] = x.z;
+    S.v[b + a] = v.x; S.v[b + S.np + a] = v.y; S.v[b + 2 * S.np + a] = v.z;
+    if (!finite3(x) || !finite3(v)) atomicOr(&S.err[ERR_UNSTABLE], 1);
+    if (S.cutoff_on) {
+        const float dx = x.x - S.xb[b + a], dy = x.y - S.xb[b + S.np + a], dz = x.z - S.xb[b + 2 * S.np + a];
+        if (!(dx * dx + dy * dy + dz * dz <= S.half_skin2)) atomicOr(guard, 1);
+    }
+}
+
+// Bonded forces of atom range [blockIdx.x * blockDim.x, +blockDim.x) of replica r:
+// fixed-point LDS accumulation, then a plain store that initialises F for the step.
+__global__ void __launch_bounds__(256) k_bonded(Dev S, int r_off, int energy)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    long long *fa = (long long *)lds_raw;
+    __shared__ long long e_acc;
+    const int r = r_off + blockIdx.y;
+    const int len = blockDim.x;
+    const int a0 = blockIdx.x * len, a1 = min(S.n, a0 + len);
+    const int tid = threadIdx.x;
+    for (int k = tid; k < 3 * len; k += len) fa[k] = 0;
+    if (tid == 0) e_acc = 0;
+    __syncthreads();
+    const size_t b = (size_t)r * 3 * S.np;
+    if (S.kind == KIND_TOY) {
+        if (tid == 0 && a0 == 0) {
+            float fx, fy;
+            const float u = toy_force(S.x[b], S.x[b + S.np], fx, fy);
+            fa[0] = fix_f(fx);
+            fa[len] = fix_f(fy);
+            if (energy) e_acc = fix_f(u);
+        }
+    } else {
+        bonded_range(S, PosGlob{S.x + b, S.np}, a0, a1, fa, len, energy ? &e_acc : nullptr, tid, len);
+    }
+    __syncthreads();
+    const int a = a0 + tid;
+    if (a < a1) {
+        S.F[b + a] = fa[tid];
+        S.F[b + S.np + a] = fa[len + tid];
+        S.F[b + 2 * S.np + a] = fa[2 * len + tid];
+    }
+    if (energy && tid == 0 && e_acc != 0) atomicAdd((unsigned long long *)&S.E[r], (unsigned long long)e_acc);
+}
+
+// Nonbonded forces of atoms [blockIdx.x * blockDim.x / P, ...) of replica r (P lanes per
+// atom), added to the bonded forces; then the closing B kick (apply_b).  The pair lists of
+// the block's atoms are rebuilt first when due (period, displacement guard, force_build).
+__global__ void __launch_bounds__(256) k_nonbonded(Dev S, long long s, int r_off, int energy, int apply_b,
+                                                   int force_build)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    float4 *xs = (float4 *)lds_raw;
+    float2 *pp = (float2 *)(xs + S.np);
+    float4 *sph = (float4 *)(pp + S.np);
+    __shared__ long long e_acc;
+    const int r = r_off + blockIdx.y;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    stage_replica(S, r, xs, pp, tid, nthr);
+    if (tid == 0) e_acc = 0;
+    bool rebuild = force_build != 0;
+    if (!force_build) {
+        if (S.cutoff_on) rebuild = ((s + 1) % S.period == 0) || S.guard[(s & 1) * S.R + r] != 0;
+        if (blockIdx.x == 0 && tid == 0) S.guard[((s + 1) & 1) * S.R + r] = 0;
+    }
+    __syncthreads();
+    const int i = blockIdx.x * (nthr / P) + tid / P;
+    const int q = tid % P;
+    const size_t b = (size_t)r * 3 * S.np;
+    if (rebuild) {
+        block_spheres(S, xs, sph, tid, nthr);
+        __syncthreads();
+        if (i < S.n) {
+            build_lane(S, r, i, q, xs, sph, !S.cutoff_on);
+            if (q == 0) {
+                S.xb[b + i] = xs[i].x; S.xb[b + S.np + i] = xs[i].y; S.xb[b + 2 * S.np + i] = xs[i].z;
+            }
+        }
+        __syncthreads();
+    }
+    long long eatom = 0;
+    if (i < S.n) {
+        float4 f = nb_lane(S, r, i, q, xs, pp, energy != 0);
+        f.x = quad_sum(f.x);
+        f.y = quad_sum(f.y);
+        f.z = quad_sum(f.z);
+        if (energy) f.w = quad_sum(f.w);
+        if (q == 0) {
+            const long long Fx = S.F[b + i] + fix_f(f.x);
+            const long long Fy = S.F[b + S.np + i] + fix_f(f.y);
+            const long long Fz = S.F[b + 2 * S.np + i] + fix_f(f.z);
+            S.F[b + i] = Fx; S.F[b + S.np + i] = Fy; S.F[b + 2 * S.np + i] = Fz;
+            const float fx = unfix_f(Fx), fy = unfix_f(Fy), fz = unfix_f(Fz);
+            if (bad_force(fx) || bad_force(fy) || bad_force(fz)) atomicOr(&S.err[ERR_UNSTABLE], 1);
+            if (apply_b) {
+                const float im = S.prm[i].w, h = S.h;
+                S.v[b + i] = kick(S.v[b + i], fx, h, im);
+                S.v[b + S.np + i] = kick(S.v[b + S.np + i], fy, h, im);
+                S.v[b + 2 * S.np + i] = kick(S.v[b + 2 * S.np + i], fz, h, im);
+            }
+            if (energy) eatom = fix_f(f.w);
+        }
+    }
+    if (energy) {
+        eatom = wave_sum_ll(eatom);
+        if ((tid & 63) == 0 && eatom != 0) lds_add(&e_acc, eatom);
+        __syncthreads();
+        if (tid == 0 && e_acc != 0) atomicAdd((unsigned long long *)&S.E[r], (unsigned long long)e_acc);
+    }
+}
+
+// observables of replicas r_off + blockIdx.x: accumulate (mode 0, workers), set the shift
+// c_j from replica 0 (mode 1), or write the values to out[r][MAX_OBS] (mode 2)
+__global__ void __launch_bounds__(256) k_obs(Dev S, int r_off, int mode, double *out)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    float4 *xs = (float4 *)lds_raw;
+    __shared__ long long red[MAX_OBS * 8 + 8];
+    __shared__ double vals[MAX_OBS];
+    const int r = r_off + blockIdx.x;
+    stage_replica(S, r, xs, nullptr, threadIdx.x, blockDim.x);
+    __syncthreads();
+    const float *vg = S.v + (size_t)r * 3 * S.np;
+    observables_wg(S, xs, vg, unfix_d(S.E[r]), red, vals, threadIdx.x, blockDim.x);
+    if (threadIdx.x == 0) {
+        if (mode == 0) accumulate_obs(S, r, vals);
+        else if (mode == 1) for (int j = 0; j < S.nobs; ++j) S.shift[j] = vals[j];
+        else for (int j = 0; j < S.nobs; ++j) out[(size_t)r * MAX_OBS + j] = vals[j];
+    }
+}
+
+// state ids of replicas r_off + blockIdx.x
+__global__ void __launch_bounds__(256) k_state(Dev S, int r_off)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    float4 *xs = (float4 *)lds_raw;
+    __shared__ long long red[8];
+    __shared__ int sbuf;
+    const int r = r_off + blockIdx.x;
+    stage_replica(S, r, xs, nullptr, threadIdx.x, blockDim.x);
+    __syncthreads();
+    const int id = state_wg(S, xs, red, &sbuf, threadIdx.x, blockDim.x);
+    if (threadIdx.x == 0) S.state[r] = id;
+}
+
+// ================================================================== persistent path
+// One workgroup per replica advances nsteps BAOAB steps.  LDS holds the replica's positions
+// (float4 with the scaled charge), the per-atom LJ parameters, the fixed-point force
+// accumulators, block spheres and reduction scratch; each thread keeps the velocities and
+// forces of up to CHMAX atoms (atoms tid, tid + BT, ...) in registers.  Per step:
+// B A O A (own atoms) -> pair-list rebuild when due -> bonded terms (LDS atomics) ->
+// pair forces (P lanes per atom) -> closing B; every t_GR steps (t counted from t0) the
+// observables of workers are accumulated.  With state_end the state id is written at the end.
+__global__ void __launch_bounds__(1024) k_persist(Dev S, long long s0, int nsteps, int t0, int sample,
+                                                  int state_end)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int np = S.np, n = S.n;
+    long long *fa = (long long *)lds_raw;                 // [3][np]
+    long long *red = fa + 3 * np;                          // [MAX_OBS * 8 + 8]
+    double *vals = (double *)(red + MAX_OBS * 8 + 8);      // [MAX_OBS]
+    float4 *xs = (float4 *)(vals + MAX_OBS);               // [np]
+    float2 *pp = (float2 *)(xs + np);                      // [np]
+    float4 *sph = (float4 *)(pp + np);                     // [nblk]
+    __shared__ int sbuf;
+    const int r = blockIdx.x;
+    const int tid = threadIdx.x, BT = blockDim.x;
+    const size_t b = (size_t)r * 3 * np;
+    float *xg = S.x + b, *vg = S.v + b, *xbg = S.xb + b;
+    long long *Fg = S.F + b;
+
+    stage_replica(S, r, xs, pp, tid, BT);
+    float vr[CHMAX][3], Fr[CHMAX][3], imr[CHMAX], sdr[CHMAX];
+#pragma unroll
+    for (int c = 0; c < CHMAX; ++c) {
+        const int a = c * BT + tid;
+        if (a < n) {
+            for (int d = 0; d < 3; ++d) { vr[c][d] = vg[d * np + a]; Fr[c][d] = unfix_f(Fg[d * np + a]); }
+            imr[c] = S.prm[a].w;
+            sdr[c] = S.sd[a];
+        } else {
+            for (int d = 0; d < 3; ++d) { vr[c][d] = 0.f; Fr[c][d] = 0.f; }
+            imr[c] = 0.f; sdr[c] = 0.f;
+        }
+    }
+    bool need = S.need_build[r] != 0;
+    __syncthreads();
+    if (tid == 0) S.need_build[r] = 0;
+    const bool toy = S.kind == KIND_TOY;
+
+    for (int step = 0; step < nsteps; ++step) {
+        const long long s = s0 + step;
+        const int tl = t0 + step + 1;
+        const bool samp = sample && r >= 1 && (tl % S.t_gr == 0);
+        const bool energy = samp && S.need_energy;
+        int hit = 0, bad = 0;
+#pragma unroll
+        for (int c = 0; c < CHMAX; ++c) {
+            const int a = c * BT + tid;
+            if (a < n) {
+                float3 x = make_float3(xs[a].x, xs[a].y, xs[a].z);
+                float3 v = make_float3(vr[c][0], vr[c][1], vr[c][2]);
+                integrate_baoa(S, a, r, s, x, v, make_float3(Fr[c][0], Fr[c][1], Fr[c][2]), imr[c], sdr[c]);
+                xs[a].x = x.x; xs[a].y = x.y; xs[a].z = x.z;
+                vr[c][0] = v.x; vr[c][1] = v.y; vr[c][2] = v.z;
+                bad |= !(finite3(x) && finite3(v));
+                if (S.cutoff_on) {
+                    const float dx = x.x - xbg[a], dy = x.y - xbg[np + a], dz = x.z - xbg[2 * np + a];
+                    hit |= !(dx * dx + dy * dy + dz * dz <= S.half_skin2);
+                }
+            }
+        }
+        if (bad) atomicOr(&S.err[ERR_UNSTABLE], 1);
+        const int any_hit = __syncthreads_or(hit);
+        if (S.cutoff_on && (need || any_hit || ((s + 1) % S.period == 0))) {
+            block_spheres(S, xs, sph, tid, BT);
+            __syncthreads();
+            for (int L = tid; L < n * P; L += BT) {
+                const int i = L / P, q = L % P;
+                build_lane(S, r, i, q, xs, sph, false);
+                if (q == 0) { xbg[i] = xs[i].x; xbg[np + i] = xs[i].y; xbg[2 * np + i] = xs[i].z; }
+            }
+            need = false;
+        }
+        for (int k = tid; k < 3 * np; k += BT) fa[k] = 0;
+        if (tid == 0) red[MAX_OBS * 8] = 0;
+        __syncthreads();
+        if (toy) {
+            if (tid == 0) {
+                float fx, fy;
+                const float u = toy_force(xs[0].x, xs[0].y, fx, fy);
+                fa[0] = fix_f(fx);
+                fa[np] = fix_f(fy);
+                if (energy) red[MAX_OBS * 8] = fix_f(u);
+            }
+        } else {
+            bonded_range(S, PosLDS{xs}, 0, n, fa, np, energy ? &red[MAX_OBS * 8] : nullptr, tid, BT);
+            for (int L0 = 0; L0 < n * P; L0 += BT) {
+                const int L = L0 + tid;
+                const int i = L / P, q = L % P;
+                long long eatom = 0;
+                if (L < n * P) {
+                    float4 f = nb_lane(S, r, i, q, xs, pp, energy);
+                    f.x = quad_sum(f.x);
+                    f.y = quad_sum(f.y);
+                    f.z = quad_sum(f.z);
+                    if (energy) f.w = quad_sum(f.w);
+                    if (q == 0) {
+                        lds_add(&fa[i], fix_f(f.x));
+                        lds_add(&fa[np + i], fix_f(f.y));
+                        lds_add(&fa[2 * np + i], fix_f(f.z));
+                        if (energy) eatom = fix_f(f.w);
+                    }
+                }
+                if (energy) {
+                    eatom = wave_sum_ll(eatom);
+                    if ((tid & 63) == 0 && eatom != 0) lds_add(&red[MAX_OBS * 8], eatom);
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < CHMAX; ++c) {
+            const int a = c * BT + tid;
+            if (a < n) {
+                for (int d = 0; d < 3; ++d) {
+                    Fr[c][d] = unfix_f(fa[d * np + a]);
+                    vr[c][d] = kick(vr[c][d], Fr[c][d], S.h, imr[c]);
+                }
+                if (bad_force(Fr[c][0]) || bad_force(Fr[c][1]) || bad_force(Fr[c][2])) atomicOr(&S.err[ERR_UNSTABLE], 1);
+            }
+        }
+        if (samp) {
+#pragma unroll
+            for (int c = 0; c < CHMAX; ++c) {
+                const int a = c * BT + tid;
+                if (a < n) for (int d = 0; d < 3; ++d) vg[d * np + a] = vr[c][d];
+            }
+            __syncthreads();
+            observables_wg(S, xs, vg, unfix_d(red[MAX_OBS * 8]), red, vals, tid, BT);
+            if (tid == 0) accumulate_obs(S, r, vals);
+        }
+        __syncthreads();
+    }
+    // write back the replica state
+#pragma unroll
+    for (int c = 0; c < CHMAX; ++c) {
+        const int a = c * BT + tid;
+        if (a < n) {
+            for (int d = 0; d < 3; ++d) vg[d * np + a] = vr[c][d];
+            xg[a] = xs[a].x; xg[np + a] = xs[a].y; xg[2 * np + a] = xs[a].z;
+            if (nsteps > 0) { Fg[a] = fa[a]; Fg[np + a] = fa[np + a]; Fg[2 * np + a] = fa[2 * np + a]; }
+        }
+    }
+    if (state_end) {
+        __syncthreads();
+        const int id = state_wg(S, xs, red, &sbuf, tid, BT);
+        if (tid == 0) S.state[r] = id;
+    }
+}
+
+// ================================================================== Gen.ParRep bookkeeping
+// Pairwise sum over k = 0..m-1 of f(k): the halving recursion (lower half first) unrolled
+// with an explicit stack, so that the rounding matches a recursive evaluation exactly.
+template <class Fn>
+__device__ double pairwise_sum(int m, Fn f)
+{
+    if (m <= 0) return 0.0;
+    int lo_s[40], m_s[40], st_s[40];
+    double left_s[40];
+    int sp = 1;
+    lo_s[0] = 0; m_s[0] = m; st_s[0] = 0;
+    double val = 0.0;
+    bool ret = false;
+    for (;;) {
+        const int t = sp - 1;
+        if (!ret) {
+            if (m_s[t] == 1) {
+                val = f(lo_s[t]);
+                ret = true;
+                if (--sp == 0) return val;
+                continue;
+            }
+            st_s[t] = 0;
+            lo_s[sp] = lo_s[t]; m_s[sp] = m_s[t] / 2; st_s[sp] = 0; ++sp;
+        } else if (st_s[t] == 0) {
+            left_s[t] = val;
+            st_s[t] = 1;
+            const int h = m_s[t] / 2;
+            lo_s[sp] = lo_s[t] + h; m_s[sp] = m_s[t] - h; st_s[sp] = 0; ++sp;
+            ret = false;
+        } else {
+            val = left_s[t] + val;
+            if (--sp == 0) return val;
+        }
+    }
+}
+
+// Gelman-Rubin R-hat (Eq. 3) of one observable over nw workers from shifted sums
+template <class F1, class F2>
+__device__ double rhat_dev(int nw, long long n, F1 s1, F2 s2)
+{
+    const double dn = (double)n, dw = (double)nw;
+    const double m1 = pairwise_sum(nw, [&](int k) { return s1(k) / dn; }) / dw;
+    const double m2 = pairwise_sum(nw, [&](int k) { return s2(k) / dn; }) / dw;
+    const double m1sq = m1 * m1;
+    const double num = m2 - m1sq;
+    const double den = pairwise_sum(nw, [&](int k) {
+        const double ob = s1(k) / dn;
+        const double a = s2(k) / dn;
+        const double o2 = ob * ob;
+        return a - o2;
+    }) / dw;
+    return den > 0.0 ? num / den : __longlong_as_double(0x7FF0000000000000LL);
+}
+
+// Fleming-Viot plan: survivors S (ascending), each exited worker r copies S[(u |S|) >> 32]
+// with u the first Philox word of (0, s, r, stream 2); -2 everywhere if S is empty.
+template <class Ex>
+__device__ void fv_plan_dev(uint32_t k0, uint32_t k1, long long s, int R, Ex exited, int *donor, int *surv)
+{
+    int ns = 0;
+    for (int r = 1; r < R; ++r) if (!exited(r)) surv[ns++] = r;
+    donor[0] = ns == 0 ? -2 : -1;
+    for (int r = 1; r < R; ++r) {
+        if (ns == 0) { donor[r] = -2; continue; }
+        if (!exited(r)) { donor[r] = -1; continue; }
+        const uint4 w = philox_ctr(0u, s, (uint32_t)r, STREAM_BRANCH, k0, k1);
+        const unsigned long long pick = ((unsigned long long)w.x * (unsigned long long)ns) >> 32;
+        donor[r] = surv[pick];
+    }
+}
+
+// Exit vote of Eq. 5 on first-exit check indices
+__device__ void vote_dev(int R, const long long *fec, long long t_check, long long *M, int *k, long long *tau)
+{
+    long long best = 0;
+    int kk = 0;
+    for (int r = 0; r < R; ++r) {
+        if (fec[r] <= 0) continue;
+        if (best == 0 || fec[r] < best) { best = fec[r]; kk = r + 1; }
+    }
+    *M = best;
+    *k = kk;
+    *tau = best > 0 ? ((long long)R * (best - 1) + kk) * t_check : 0;
+}
+
+// Per-check bookkeeping (one workgroup).  mode: CHK_STATE (decorrelation: report replica 0),
+// CHK_DEPHASE (reference-exit test, branching plan into donor[], R-hat over workers with the
+// planned clones' sums), CHK_PARALLEL (first exiting replica), CHK_ADVANCE (record first
+// exit checks, R-hat computed and reported, nothing acted on).
+__global__ void __launch_bounds__(64) k_check(Dev S, int mode, long long s, int omega, int nrep, long long nsamp,
+                                              int check_index, Status *st, int *donor, int *surv, long long *fec)
+{
+    const int tid = threadIdx.x;
+    __shared__ int no_surv;
+    if (tid == 0) {
+        st->mode = mode;
+        st->ref_exited = 0;
+        st->n_exited = 0;
+        st->n_surv = 0;
+        st->k = 0;
+        st->to_state = S.state[0];
+        for (int e = 0; e < 4; ++e) st->err[e] = S.err[e];
+        no_surv = 0;
+        if (mode == CHK_DEPHASE) {
+            if (S.state[0] != omega) {
+                st->ref_exited = 1;
+                for (int r = 0; r < nrep; ++r) donor[r] = -1;
+            } else {
+                auto ex = [&](int r) { return S.state[r] != omega; };
+                fv_plan_dev(S.key0, S.key1, s, nrep, ex, donor, surv);
+                int ne = 0;
+                for (int r = 1; r < nrep; ++r) ne += ex(r);
+                st->n_exited = ne;
+                st->n_surv = nrep - 1 - ne;
+                if (nrep > 1 && donor[1] == -2) {
+                    no_surv = 1;
+                    donor[0] = -1;
+                    for (int r = 1; r < nrep; ++r) donor[r] = 0;   // re-copy every worker from the reference
+                }
+            }
+        } else if (mode == CHK_PARALLEL) {
+            for (int r = 0; r < nrep; ++r)
+                if (S.state[r] != omega) { st->k = r + 1; st->to_state = S.state[r]; break; }
+        } else if (mode == CHK_ADVANCE) {
+            for (int r = 0; r < nrep; ++r)
+                if (fec[r] == 0 && S.state[r] != omega) fec[r] = check_index;
+        }
+    }
+    __syncthreads();
+    if ((mode == CHK_DEPHASE || mode == CHK_ADVANCE) && tid < MAX_OBS) {
+        double rh = __longlong_as_double(0x7FF0000000000000LL);
+        const bool skip = (mode == CHK_DEPHASE && no_surv) || nsamp < 1 || tid >= S.nobs;
+        if (!skip) {
+            const int j = tid;
+            auto src = [&](int k) {
+                int r = k + 1;
+                if (mode == CHK_DEPHASE && donor[r] >= 0) r = donor[r];
+                return r;
+            };
+            auto s1 = [&](int k) { return S.acc[((size_t)src(k) * MAX_OBS + j) * 2]; };
+            auto s2 = [&](int k) { return S.acc[((size_t)src(k) * MAX_OBS + j) * 2 + 1]; };
+            rh = rhat_dev(nrep - 1, nsamp, s1, s2);
+        }
+        st->rhat[tid] = rh;
+    }
+}
+
+// Copies (x, v, F) of replica donor[r] into replica r for every r with donor[r] >= 0 and
+// marks r for a pair-list rebuild; observable sums are copied too (acc_mode 1), or cleared
+// when the donor is the reference walker (a fresh broadcast).
+__global__ void __launch_bounds__(256) k_clone(Dev S, const int *donor, int acc_mode)
+{
+    const int r = blockIdx.y;
+    const int d = donor[r];
+    if (d < 0 || d == r) return;
+    const size_t bs = (size_t)d * 3 * S.np, bd = (size_t)r * 3 * S.np;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < 3 * S.np; k += gridDim.x * blockDim.x) {
+        S.x[bd + k] = S.x[bs + k];
+        S.v[bd + k] = S.v[bs + k];
+        S.F[bd + k] = S.F[bs + k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) S.need_build[r] = 1;
+    if (acc_mode && blockIdx.x == 0 && threadIdx.x < 2 * MAX_OBS) {
+        S.acc[(size_t)r * 2 * MAX_OBS + threadIdx.x] = d == 0 ? 0.0 : S.acc[(size_t)d * 2 * MAX_OBS + threadIdx.x];
+    }
+}
+
+// Maxwell-Boltzmann velocities of replica 0 (stream 1, step 0)
+__global__ void __launch_bounds__(256) k_init_vel(Dev S, float kT)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= S.n) return;
+    const float3 g = gauss3(philox_ctr((uint32_t)a, 0, 0u, STREAM_INIT, S.key0, S.key1));
+    const float sdev = sqrtf(kT * S.prm[a].w);
+    S.v[a] = sdev * g.x;
+    S.v[S.np + a] = sdev * g.y;
+    S.v[2 * S.np + a] = S.kind == KIND_TOY ? 0.0f : sdev * g.z;
+}
+
+// ------------------------------------------------------------------ building blocks
+__global__ void __launch_bounds__(256) k_noise_test(uint32_t k0, uint32_t k1, int replica, long long step, int stream,
+                                                    int n, uint32_t *words, float *gauss)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n) return;
+    const uint4 w = philox_ctr((uint32_t)a, step, (uint32_t)replica, (uint32_t)stream, k0, k1);
+    const float3 g = gauss3(w);
+    words[4 * a] = w.x; words[4 * a + 1] = w.y; words[4 * a + 2] = w.z; words[4 * a + 3] = w.w;
+    gauss[3 * a] = g.x; gauss[3 * a + 1] = g.y; gauss[3 * a + 2] = g.z;
+}
+
+__global__ void k_fvplan_test(uint32_t k0, uint32_t k1, long long s, int R, const uint8_t *exited, int *donor, int *surv)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        auto ex = [&](int r) { return exited[r] != 0; };
+        fv_plan_dev(k0, k1, s, R, ex, donor, surv);
+    }
+}
+
+__global__ void k_rhat_test(int nw, int nobs, long long n, const double *S1, const double *S2, double *out)
+{
+    const int j = threadIdx.x;
+    if (j >= nobs) return;
+    auto s1 = [&](int k) { return S1[(size_t)k * nobs + j]; };
+    auto s2 = [&](int k) { return S2[(size_t)k * nobs + j]; };
+    out[j] = rhat_dev(nw, n, s1, s2);
+}
+
+__global__ void k_vote_test(int R, const long long *fec, long long t_check, long long *out)
+{
+    if (threadIdx.x == 0) {
+        long long M, tau;
+        int k;
+        vote_dev(R, fec, t_check, &M, &k, &tau);
+        out[0] = M; out[1] = k; out[2] = tau;
+    }
+}
+
+} // namespace gpr
