@@ -1,0 +1,178 @@
+"""Throughput of the Gen.ParRep hot path on one MI355X.
+
+Workload: the 2,432-atom receptor-ligand system (2,400-atom restrained receptor chain + a
+32-atom ligand in its pocket, 1.0 nm cutoff with reaction field, BAOAB at 1 fs) with 64
+replicas.  One step = one BAOAB step of all 64 replicas with everything the dephasing
+stage does around it: pair-list maintenance (every 10 steps and on the displacement
+guard), bonded and nonbonded forces, observables of the workers every t_GR = 50 steps,
+and every t_check = 1000 steps the state test of every replica, the Fleming-Viot
+branching plan, the Gelman-Rubin statistics and the exit vote (computed, not acted on, so
+that the work per step is fixed).
+
+The product path (persistent kernel) is timed, then the plain one-launch-per-kernel-per-step
+path on the same system and seeds.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# published MI355X peaks
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+# algorithmic FLOP counts (FMA = 2) per unit of work
+FLOP_PAIR = 40          # one in-cutoff nonbonded pair, force only, counted once per unordered pair
+FLOP_BOND, FLOP_ANGLE, FLOP_TORSION, FLOP_RESTRAINT, FLOP_PAIR14 = 25, 60, 110, 12, 45
+FLOP_ATOM_BAOAB = 20    # kicks, drifts and the Ornstein-Uhlenbeck update of one atom
+
+
+def in_cutoff_pairs(spec, q):
+    """Number of nonbonded pairs (not excluded, not 1-4) closer than the cutoff."""
+    n = spec["n_atoms"]
+    rc2 = spec["cutoff"] ** 2
+    x = q.T
+    skip = set()
+    for a, b in np.concatenate([spec["exclusions"], spec["pairs14"]]):
+        skip.add((min(a, b), max(a, b)))
+    total = 0
+    for i0 in range(0, n, 256):
+        d = x[i0:i0 + 256, None, :] - x[None, :, :]
+        r2 = (d * d).sum(-1)
+        ii, jj = np.nonzero(r2 < rc2)
+        keep = jj > ii + i0
+        total += int(keep.sum())
+        for i, j in zip(ii[keep] + i0, jj[keep]):
+            if j - i <= 3 and (i, j) in skip:
+                total -= 1
+    return total
+
+
+def flops_per_replica_step(spec, pairs):
+    return (pairs * FLOP_PAIR + len(spec["bonds"]) * FLOP_BOND + len(spec["angles"]) * FLOP_ANGLE
+            + len(spec["torsions"]) * FLOP_TORSION + len(spec["restraints"]) * FLOP_RESTRAINT
+            + len(spec["pairs14"]) * FLOP_PAIR14 + spec["n_atoms"] * FLOP_ATOM_BAOAB)
+
+
+def timed_advance(sysobj, steps):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sysobj.advance(steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(spec, seconds=15.0):
+    """The FP64 oracle, single-threaded, on a bounded sample of the same workload: a few
+    replicas for as many steps as fit in about ``seconds``."""
+    import oracle
+    R = 4
+    o = oracle.System(dict(spec, n_replicas=R))
+    t0 = time.perf_counter()
+    o.advance(1)
+    one = time.perf_counter() - t0
+    steps = max(1, int(seconds / max(one, 1e-6)))
+    t0 = time.perf_counter()
+    o.advance(steps)
+    dt = time.perf_counter() - t0
+    return dict(value=R * steps / dt, unit="replica-steps/s", cores=1, kind="oracle",
+                sample="%d replicas x %d steps of the 2,432-atom system (FP64, brute-force pairs)" % (R, steps),
+                atom_steps_per_s=R * steps * spec["n_atoms"] / dt)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the replicas of one system share one device "
+              "(multi-GPU replica sharding is not part of this build); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import gpr_synth as G
+    import paper_1807_02431_amd as gpr
+
+    spec = G.config("rl2432")
+    R, n = spec["n_replicas"], spec["n_atoms"]
+    stream = torch.cuda.current_stream()
+
+    # ------------------------------------------------------------ product path
+    print("# persistent path: warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
+    ps = gpr.System(spec, path=gpr.PATH_PERSISTENT, stream=stream)
+    ps.advance(args.warmup)
+    ps.profile(True)
+    print("# persistent path: timing %d steps" % args.steps, file=sys.stderr, flush=True)
+    t_p = timed_advance(ps, args.steps)
+    kms, klaunch = ps.profile_read()
+    ps.profile(False)
+    q_samples = [ps.get_state(r)[0] for r in (0, R // 2, R - 1)]
+    pairs = float(np.mean([in_cutoff_pairs(spec, q) for q in q_samples]))
+    frs = flops_per_replica_step(spec, pairs)
+
+    # ------------------------------------------------------------ plain path
+    plain = None
+    if not args.no_plain:
+        print("# plain path: warmup %d, timing %d steps" % (args.warmup, args.steps), file=sys.stderr, flush=True)
+        pl = gpr.System(spec, path=gpr.PATH_PLAIN, stream=stream)
+        pl.advance(args.warmup)
+        t_pl = timed_advance(pl, args.steps)
+        pl.profile(True)
+        pl.advance(min(args.steps, 1000))
+        nb_ms, nb_n = pl.profile_read()
+        pl.profile(False)
+        plain = dict(replica_steps_per_s=R * args.steps / t_pl, atom_steps_per_s=R * n * args.steps / t_pl,
+                     ms_per_step=1e3 * t_pl / args.steps, launches_per_step=3,
+                     pair_kernel_us=1e3 * nb_ms / max(nb_n, 1))
+
+    cpu = None if args.no_cpu else cpu_baseline(spec)
+
+    steps_per_launch = args.steps / max(klaunch, 1)
+    avg_launch_s = kms / 1e3 / max(klaunch, 1)
+    achieved = frs * R * steps_per_launch / avg_launch_s / 1e12
+    value = R * args.steps / t_p
+    out = {
+        "metric": "replica-steps/s & atom-steps/s, 2,432 atoms x 64 replicas, vs plain GPU path",
+        "value": value,
+        "unit": "replica-steps/s",
+        "atom_steps_per_s": value * n,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t_p / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "speedup_vs_plain": (value / plain["replica_steps_per_s"]) if plain else None,
+        "plain_path": plain,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "receptor-ligand, 2,432 atoms (2,400 restrained receptor + 32 ligand) x 64 replicas, "
+                               "cutoff 1.0 nm reaction field, BAOAB dt 1 fs, t_GR 50, t_check 1000",
+                   "n_atoms": n, "n_replicas": R, "path": "persistent"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "k_persist", "avg_launch_us": avg_launch_s * 1e6,
+                     "steps_per_launch": steps_per_launch, "flop_per_replica_step": frs,
+                     "in_cutoff_pairs_per_replica": pairs},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -268,6 +268,14 @@ gpr_status gpr_set_state(gpr_system *sys, int32_t r, const double *q, const doub
  * the measurement harness. */
 gpr_status gpr_advance(gpr_system *sys, int64_t nsteps, int64_t *first_exit_check);
 
+/* Timing of the dominant stepping kernel (the persistent kernel on the persistent path,
+ * the pair-force kernel on the plain path) with HIP events recorded on the system's
+ * stream around each launch.  gpr_profile enables (1) or disables (0) recording and
+ * clears the totals; gpr_profile_read waits for the stream and returns the summed
+ * duration in ms and the number of launches timed since the last clear. */
+gpr_status gpr_profile(gpr_system *sys, int32_t enable);
+gpr_status gpr_profile_read(gpr_system *sys, double *ms, int64_t *launches);
+
 /* Observable accumulators of replicas [0, R): n (samples) and, per replica r and observable
  * j, S1[r][j] = sum (O - c_j), S2[r][j] = sum (O - c_j)^2, shift[j] = c_j = O_j of replica 0
  * at dephasing start.  Host buffers, each may be NULL. */

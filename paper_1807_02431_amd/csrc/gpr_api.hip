@@ -52,6 +52,12 @@ struct gpr_system {
     long long *fec = nullptr;
     size_t lds_persist = 0, lds_nb = 0, lds_stage = 0;
     int persist_ok = 0;
+    // event timing of the dominant stepping kernel
+    bool prof = false;
+    std::vector<hipEvent_t> ev_a, ev_b;
+    size_t ev_used = 0;
+    double prof_ms = 0.0;
+    long long prof_n = 0;
     std::string err;
 };
 
@@ -130,11 +136,50 @@ long long count_samples(long long t_old, long long t_new, int t_gr) { return t_n
 
 } // namespace
 
+// event pair around the next timed launch (created on first use, reused afterwards)
+static hipError_t prof_begin(gpr_system *S)
+{
+    if (!S->prof) return hipSuccess;
+    if (S->ev_used == S->ev_a.size()) {
+        hipEvent_t a, b;
+        hipError_t e = hipEventCreate(&a);
+        if (e != hipSuccess) return e;
+        e = hipEventCreate(&b);
+        if (e != hipSuccess) return e;
+        S->ev_a.push_back(a);
+        S->ev_b.push_back(b);
+    }
+    return hipEventRecord(S->ev_a[S->ev_used], S->stream);
+}
+
+static hipError_t prof_end(gpr_system *S)
+{
+    if (!S->prof) return hipSuccess;
+    hipError_t e = hipEventRecord(S->ev_b[S->ev_used], S->stream);
+    S->ev_used++;
+    return e;
+}
+
+// after the stream has drained: fold the recorded pairs into the totals
+static hipError_t prof_collect(gpr_system *S)
+{
+    for (size_t k = 0; k < S->ev_used; ++k) {
+        float ms = 0.f;
+        hipError_t e = hipEventElapsedTime(&ms, S->ev_a[k], S->ev_b[k]);
+        if (e != hipSuccess) return e;
+        S->prof_ms += ms;
+        S->prof_n += 1;
+    }
+    S->ev_used = 0;
+    return hipSuccess;
+}
+
 // ------------------------------------------------------------------ launches
 // forces of replicas [r_off, r_off + nrep) at their current positions.  Stepping calls
 // (force_build = 0) rely on k_integrate to clear the energies and maintain the list guard;
 // force-only calls (force_build = 1) rebuild the lists and clear the energies here.
-static gpr_status launch_forces(gpr_system *S, int r_off, int nrep, long long s, int energy, int apply_b, int force_build)
+static gpr_status launch_forces(gpr_system *S, int r_off, int nrep, long long s, int energy, int apply_b, int force_build,
+                                bool timed = false)
 {
     const int BTB = 256, BTN = 256;
     if (energy && force_build) {
@@ -144,8 +189,10 @@ static gpr_status launch_forces(gpr_system *S, int r_off, int nrep, long long s,
     hipLaunchKernelGGL(k_bonded, gb, dim3(BTB), 3 * BTB * sizeof(long long), S->stream, S->d, r_off, energy);
     LAUNCHCHK(S);
     dim3 gn((S->n * P + BTN - 1) / BTN, nrep);
+    if (timed) HIPCHK(S, prof_begin(S));
     hipLaunchKernelGGL(k_nonbonded, gn, dim3(BTN), S->lds_nb, S->stream, S->d, s, r_off, energy, apply_b, force_build);
     LAUNCHCHK(S);
+    if (timed) HIPCHK(S, prof_end(S));
     return GPR_OK;
 }
 
@@ -165,9 +212,11 @@ static gpr_status run_steps(gpr_system *S, int nrep, long long nsteps, long long
         while (done < nsteps) {
             const int chunk = (int)std::min<long long>(nsteps - done, 1 << 20);
             const bool last = done + chunk == nsteps;
+            HIPCHK(S, prof_begin(S));
             hipLaunchKernelGGL(k_persist, dim3(nrep), dim3(S->bt_persist), S->lds_persist, S->stream, S->d,
                                S->s + done, chunk, (int)(t0 + done), sample ? 1 : 0, (state_end && last) ? 1 : 0);
             LAUNCHCHK(S);
+            HIPCHK(S, prof_end(S));
             done += chunk;
         }
         S->s += nsteps;
@@ -181,7 +230,7 @@ static gpr_status run_steps(gpr_system *S, int nrep, long long nsteps, long long
         const int energy = (samp && S->d.need_energy) ? 1 : 0;
         hipLaunchKernelGGL(k_integrate, gi, dim3(BTI), 0, S->stream, S->d, S->s, 0, energy);
         LAUNCHCHK(S);
-        gpr_status rc = launch_forces(S, 0, nrep, S->s, energy, 1, 0);
+        gpr_status rc = launch_forces(S, 0, nrep, S->s, energy, 1, 0, true);
         if (rc) return rc;
         S->s += 1;
         if (samp) {
@@ -207,6 +256,7 @@ static gpr_status check(gpr_system *S, int mode, int nrep, int check_index)
     }
     HIPCHK(S, hipMemcpyAsync(S->st_host, S->st_dev, sizeof(Status), hipMemcpyDeviceToHost, S->stream));
     HIPCHK(S, hipStreamSynchronize(S->stream));
+    HIPCHK(S, prof_collect(S));
     if (S->st_host->err[ERR_UNSTABLE]) return fail(S, GPR_EUNSTABLE, "non-finite or overflowing state");
     if (S->st_host->err[ERR_LIST]) return fail(S, GPR_EDEVICE, "pair-list capacity exceeded");
     return GPR_OK;
@@ -246,9 +296,11 @@ static gpr_status state_of_ref(gpr_system *S, int *out)
 extern "C" void gpr_system_destroy(gpr_system *S)
 {
     if (!S) return;
-    if (S->stream) hipStreamSynchronize(S->stream);
-    for (void *p : S->bufs) hipFree(p);
-    if (S->st_host) hipHostFree(S->st_host);
+    if (S->stream) (void)hipStreamSynchronize(S->stream);
+    for (void *p : S->bufs) (void)hipFree(p);
+    for (hipEvent_t e : S->ev_a) (void)hipEventDestroy(e);
+    for (hipEvent_t e : S->ev_b) (void)hipEventDestroy(e);
+    if (S->st_host) (void)hipHostFree(S->st_host);
     delete S;
 }
 
@@ -627,6 +679,27 @@ extern "C" gpr_status gpr_set_launch(gpr_system *S, int32_t block_threads, int32
     return GPR_OK;
 }
 
+extern "C" gpr_status gpr_profile(gpr_system *S, int32_t enable)
+{
+    if (!S) return fail(nullptr, GPR_EINVAL, "NULL system");
+    HIPCHK(S, hipStreamSynchronize(S->stream));
+    HIPCHK(S, prof_collect(S));
+    S->prof = enable != 0;
+    S->prof_ms = 0.0;
+    S->prof_n = 0;
+    return GPR_OK;
+}
+
+extern "C" gpr_status gpr_profile_read(gpr_system *S, double *ms, int64_t *launches)
+{
+    if (!S) return fail(nullptr, GPR_EINVAL, "NULL system");
+    HIPCHK(S, hipStreamSynchronize(S->stream));
+    HIPCHK(S, prof_collect(S));
+    if (ms) *ms = S->prof_ms;
+    if (launches) *launches = S->prof_n;
+    return GPR_OK;
+}
+
 // ------------------------------------------------------------------ queries
 extern "C" double gpr_simulated_time(const gpr_system *S) { return S ? (double)S->tsim * S->dt : NAN; }
 extern "C" int64_t gpr_simulated_steps(const gpr_system *S) { return S ? S->tsim : -1; }
@@ -902,6 +975,7 @@ extern "C" gpr_status gpr_advance(gpr_system *S, int64_t nsteps, int64_t *first_
     int err[4];
     HIPCHK(S, hipMemcpyAsync(err, S->d.err, sizeof err, hipMemcpyDeviceToHost, S->stream));
     HIPCHK(S, hipStreamSynchronize(S->stream));
+    HIPCHK(S, prof_collect(S));
     if (err[ERR_UNSTABLE]) return fail(S, GPR_EUNSTABLE, "non-finite or overflowing state");
     if (err[ERR_LIST]) return fail(S, GPR_EDEVICE, "pair-list capacity exceeded");
     if (first_exit_check) for (int r = 0; r < S->R; ++r) first_exit_check[r] = f[r];
@@ -920,7 +994,7 @@ static hipError_t tmp_alloc(std::vector<void *> &v, T **p, size_t count)
 
 struct TmpBufs {
     std::vector<void *> v;
-    ~TmpBufs() { for (void *p : v) hipFree(p); }
+    ~TmpBufs() { for (void *p : v) (void)hipFree(p); }
 };
 
 #define TMPCHK(call)                                                                                \

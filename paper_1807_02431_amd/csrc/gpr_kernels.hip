@@ -849,8 +849,17 @@ __global__ void __launch_bounds__(64) k_check(Dev S, int mode, long long s, int 
             for (int r = 0; r < nrep; ++r)
                 if (S.state[r] != omega) { st->k = r + 1; st->to_state = S.state[r]; break; }
         } else if (mode == CHK_ADVANCE) {
-            for (int r = 0; r < nrep; ++r)
-                if (fec[r] == 0 && S.state[r] != omega) fec[r] = check_index;
+            // first exit checks for the vote, and the branching plan of this check (reported,
+            // not acted on)
+            auto ex = [&](int r) { return S.state[r] != omega; };
+            int ne = 0;
+            for (int r = 0; r < nrep; ++r) {
+                if (fec[r] == 0 && ex(r)) fec[r] = check_index;
+                ne += r > 0 && ex(r);
+            }
+            fv_plan_dev(S.key0, S.key1, s, nrep, ex, donor, surv);
+            st->n_exited = ne;
+            st->n_surv = nrep - 1 - ne;
         }
     }
     __syncthreads();
@@ -863,7 +872,7 @@ __global__ void __launch_bounds__(64) k_check(Dev S, int mode, long long s, int 
                 int r = k + 1;
                 if (mode == CHK_DEPHASE && donor[r] >= 0) r = donor[r];
                 return r;
-            };
+            };   // the sums a worker holds after this check's branching
             auto s1 = [&](int k) { return S.acc[((size_t)src(k) * MAX_OBS + j) * 2]; };
             auto s2 = [&](int k) { return S.acc[((size_t)src(k) * MAX_OBS + j) * 2 + 1]; };
             rh = rhat_dev(nrep - 1, nsamp, s1, s2);

@@ -98,6 +98,8 @@ SIGNATURES = {
     "gpr_set_state": (C.c_int32, [_VP, C.c_int32, _PD, _PD]),
     "gpr_advance": (C.c_int32, [_VP, C.c_int64, _P64]),
     "gpr_get_accumulators": (C.c_int32, [_VP, _P64, _PD, _PD, _PD]),
+    "gpr_profile": (C.c_int32, [_VP, C.c_int32]),
+    "gpr_profile_read": (C.c_int32, [_VP, _PD, _P64]),
     "gpr_observe": (C.c_int32, [_VP, _PD, _PI]),
     "gpr_philox_noise": (C.c_int32, [C.c_uint64, C.c_int32, C.c_int64, C.c_int32, C.c_int32,
                                      C.POINTER(C.c_uint32), C.POINTER(C.c_float)]),
@@ -252,6 +254,16 @@ class System:
 
     def set_launch(self, block_threads=0, groups_per_replica=0):
         self._c(lib().gpr_set_launch(self._h, int(block_threads), int(groups_per_replica)))
+
+    def profile(self, enable=True):
+        self._c(lib().gpr_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """(summed ms, launches) of the dominant stepping kernel since profile() was called."""
+        ms = C.c_double()
+        n = C.c_int64()
+        self._c(lib().gpr_profile_read(self._h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
     # -------------------------------------------------------------- queries
     def energy_forces(self, r0=0, nr=None):
