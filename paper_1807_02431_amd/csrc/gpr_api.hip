@@ -30,6 +30,7 @@ thread_local std::string g_thread_err;
 
 struct gpr_system {
     Dev d{};
+    Dev *d_dev = nullptr;     // device copy of d, passed to every kernel
     std::vector<void *> bufs;
     hipStream_t stream = nullptr;
     int path = GPR_PATH_PLAIN;
@@ -181,16 +182,16 @@ static hipError_t prof_collect(gpr_system *S)
 static gpr_status launch_forces(gpr_system *S, int r_off, int nrep, long long s, int energy, int apply_b, int force_build,
                                 bool timed = false)
 {
-    const int BTB = 256, BTN = 256;
+    const int BTB = 256, BTN = 1024;
     if (energy && force_build) {
         HIPCHK(S, hipMemsetAsync(S->d.E + r_off, 0, sizeof(long long) * nrep, S->stream));
     }
     dim3 gb((S->n + BTB - 1) / BTB, nrep);
-    hipLaunchKernelGGL(k_bonded, gb, dim3(BTB), 3 * BTB * sizeof(long long), S->stream, S->d, r_off, energy);
+    hipLaunchKernelGGL(k_bonded, gb, dim3(BTB), 3 * BTB * sizeof(long long), S->stream, S->d_dev, r_off, energy);
     LAUNCHCHK(S);
     dim3 gn((S->n * P + BTN - 1) / BTN, nrep);
     if (timed) HIPCHK(S, prof_begin(S));
-    hipLaunchKernelGGL(k_nonbonded, gn, dim3(BTN), S->lds_nb, S->stream, S->d, s, r_off, energy, apply_b, force_build);
+    hipLaunchKernelGGL(k_nonbonded, gn, dim3(BTN), S->lds_nb, S->stream, S->d_dev, s, r_off, energy, apply_b, force_build);
     LAUNCHCHK(S);
     if (timed) HIPCHK(S, prof_end(S));
     return GPR_OK;
@@ -202,7 +203,7 @@ static gpr_status run_steps(gpr_system *S, int nrep, long long nsteps, long long
 {
     if (nsteps <= 0) {
         if (state_end) {
-            hipLaunchKernelGGL(k_state, dim3(nrep), dim3(256), S->lds_stage, S->stream, S->d, 0);
+            hipLaunchKernelGGL(k_state, dim3(nrep), dim3(256), S->lds_stage, S->stream, S->d_dev, 0);
             LAUNCHCHK(S);
         }
         return GPR_OK;
@@ -213,7 +214,7 @@ static gpr_status run_steps(gpr_system *S, int nrep, long long nsteps, long long
             const int chunk = (int)std::min<long long>(nsteps - done, 1 << 20);
             const bool last = done + chunk == nsteps;
             HIPCHK(S, prof_begin(S));
-            hipLaunchKernelGGL(k_persist, dim3(nrep), dim3(S->bt_persist), S->lds_persist, S->stream, S->d,
+            hipLaunchKernelGGL(k_persist, dim3(nrep), dim3(S->bt_persist), S->lds_persist, S->stream, S->d_dev,
                                S->s + done, chunk, (int)(t0 + done), sample ? 1 : 0, (state_end && last) ? 1 : 0);
             LAUNCHCHK(S);
             HIPCHK(S, prof_end(S));
@@ -228,18 +229,18 @@ static gpr_status run_steps(gpr_system *S, int nrep, long long nsteps, long long
         const long long tl = t0 + k + 1;
         const bool samp = sample && nrep > 1 && (tl % S->t_gr == 0);
         const int energy = (samp && S->d.need_energy) ? 1 : 0;
-        hipLaunchKernelGGL(k_integrate, gi, dim3(BTI), 0, S->stream, S->d, S->s, 0, energy);
+        hipLaunchKernelGGL(k_integrate, gi, dim3(BTI), 0, S->stream, S->d_dev, S->s, 0, energy);
         LAUNCHCHK(S);
         gpr_status rc = launch_forces(S, 0, nrep, S->s, energy, 1, 0, true);
         if (rc) return rc;
         S->s += 1;
         if (samp) {
-            hipLaunchKernelGGL(k_obs, dim3(nrep - 1), dim3(256), S->lds_stage, S->stream, S->d, 1, 0, nullptr);
+            hipLaunchKernelGGL(k_obs, dim3(nrep - 1), dim3(256), S->lds_stage, S->stream, S->d_dev, 1, 0, nullptr);
             LAUNCHCHK(S);
         }
     }
     if (state_end) {
-        hipLaunchKernelGGL(k_state, dim3(nrep), dim3(256), S->lds_stage, S->stream, S->d, 0);
+        hipLaunchKernelGGL(k_state, dim3(nrep), dim3(256), S->lds_stage, S->stream, S->d_dev, 0);
         LAUNCHCHK(S);
     }
     return GPR_OK;
@@ -247,11 +248,11 @@ static gpr_status run_steps(gpr_system *S, int nrep, long long nsteps, long long
 
 static gpr_status check(gpr_system *S, int mode, int nrep, int check_index)
 {
-    hipLaunchKernelGGL(k_check, dim3(1), dim3(64), 0, S->stream, S->d, mode, S->s, S->omega, nrep, S->nsamp,
+    hipLaunchKernelGGL(k_check, dim3(1), dim3(64), 0, S->stream, S->d_dev, mode, S->s, S->omega, nrep, S->nsamp,
                        check_index, S->st_dev, S->donor, S->surv, S->fec);
     LAUNCHCHK(S);
     if (mode == CHK_DEPHASE) {
-        hipLaunchKernelGGL(k_clone, dim3((3 * S->np + 255) / 256, nrep), dim3(256), 0, S->stream, S->d, S->donor, 1);
+        hipLaunchKernelGGL(k_clone, dim3((3 * S->np + 255) / 256, nrep), dim3(256), 0, S->stream, S->d_dev, S->donor, 1);
         LAUNCHCHK(S);
     }
     HIPCHK(S, hipMemcpyAsync(S->st_host, S->st_dev, sizeof(Status), hipMemcpyDeviceToHost, S->stream));
@@ -267,7 +268,7 @@ static gpr_status copy_replica(gpr_system *S, int dst, int src)
     std::vector<int> dn(S->R, -1);
     dn[dst] = src;
     HIPCHK(S, hipMemcpyAsync(S->donor, dn.data(), sizeof(int) * S->R, hipMemcpyHostToDevice, S->stream));
-    hipLaunchKernelGGL(k_clone, dim3((3 * S->np + 255) / 256, S->R), dim3(256), 0, S->stream, S->d, S->donor, 0);
+    hipLaunchKernelGGL(k_clone, dim3((3 * S->np + 255) / 256, S->R), dim3(256), 0, S->stream, S->d_dev, S->donor, 0);
     LAUNCHCHK(S);
     return GPR_OK;
 }
@@ -277,7 +278,7 @@ static gpr_status broadcast_reference(gpr_system *S)
     std::vector<int> dn(S->R, 0);
     dn[0] = -1;
     HIPCHK(S, hipMemcpyAsync(S->donor, dn.data(), sizeof(int) * S->R, hipMemcpyHostToDevice, S->stream));
-    hipLaunchKernelGGL(k_clone, dim3((3 * S->np + 255) / 256, S->R), dim3(256), 0, S->stream, S->d, S->donor, 1);
+    hipLaunchKernelGGL(k_clone, dim3((3 * S->np + 255) / 256, S->R), dim3(256), 0, S->stream, S->d_dev, S->donor, 1);
     LAUNCHCHK(S);
     return GPR_OK;
 }
@@ -312,14 +313,15 @@ extern "C" const char *gpr_last_error(const gpr_system *S)
 static size_t persist_lds(int np)
 {
     const int nblk = (np + BLK - 1) / BLK;
-    return (size_t)3 * np * 8 + (MAX_OBS * 8 + 8) * 8 + MAX_OBS * 8 + (size_t)np * 16 + (size_t)np * 8 + (size_t)nblk * 16;
+    return (size_t)3 * np * 8 + (MAX_OBS * 8 + 8) * 8 + MAX_OBS * 8 + (size_t)np * 16 + (size_t)np * 8 +
+           (size_t)3 * np * 4 + (size_t)nblk * 16;
 }
 
 static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
 {
     const int n = D->n_atoms, R = D->n_replicas;
     S->n = n; S->R = R; S->kind = D->kind;
-    S->np = (n + 63) / 64 * 64;
+    S->np = (n + 1 + 63) / 64 * 64;   // room for the dummy atom n
     const int np = S->np;
     S->t_gr = D->t_gr; S->tcd = D->t_check_dephase; S->tcp = D->t_check_parallel;
     S->tol = D->tol; S->dt = D->dt; S->t_min = D->t_min; S->kT = D->kT;
@@ -487,8 +489,9 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
             for (int q = 0; q < P; ++q) maxsub = std::max(maxsub, cnt[q]);
         }
     }
-    d.K = std::min(65535, std::max(8, d.cutoff_on ? 2 * maxsub + 8 : maxsub + 1));
-    HIPCHK(S, dalloc(S, &d.nbl, (size_t)R * d.K * np * P));
+    const int kmax = std::max(8, d.cutoff_on ? 2 * maxsub + 8 : maxsub + 1);
+    d.Kg = std::min(16383, (kmax + 3) / 4);
+    HIPCHK(S, dalloc(S, &d.nbl, (size_t)R * d.Kg * np * P));
     HIPCHK(S, dalloc(S, &d.nbc, (size_t)R * np * P));
     HIPCHK(S, dalloc(S, &d.guard, 2 * R));
     HIPCHK(S, dalloc(S, &d.need_build, R));
@@ -504,7 +507,8 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
         mtot = 0;
         for (int k = 0; k < cnt; ++k) { groups.push_back(g[k]); mtot += D->mass[g[k]]; }
     };
-    StateDesc &st = d.st;
+    StateDesc st{};
+    std::vector<ObsDesc> obs(MAX_OBS);
     st.kind = D->state.kind;
     for (int k = 0; k < 8; ++k) st.atoms[k] = D->state.atoms[k];
     st.nbox = D->state.n_boxes;
@@ -518,7 +522,7 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
     d.need_energy = 0;
     for (int j = 0; j < D->n_obs; ++j) {
         const gpr_obs_desc &o = D->obs[j];
-        ObsDesc &od = d.obs[j];
+        ObsDesc &od = obs[j];
         od.kind = o.kind;
         for (int k = 0; k < 4; ++k) od.atoms[k] = o.atoms[k];
         od.ga_n = (o.kind == GPR_OBS_COM_DISTANCE || o.kind == GPR_OBS_RMS_VELOCITY) ? o.n_a : 0;
@@ -528,12 +532,15 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
         if (o.kind == GPR_OBS_POTENTIAL) d.need_energy = 1;
     }
     HIPCHK(S, upload(S, (int **)&d.groups, groups));
+    HIPCHK(S, upload(S, (ObsDesc **)&d.obs, obs));
+    HIPCHK(S, upload(S, (StateDesc **)&d.st, std::vector<StateDesc>(1, st)));
 
     d.h = (float)(0.5 * D->dt);
     d.c1 = (float)c1;
     d.key0 = (uint32_t)D->seed;
     d.key1 = (uint32_t)(D->seed >> 32);
     d.t_gr = D->t_gr;
+    HIPCHK(S, upload(S, &S->d_dev, std::vector<Dev>(1, d)));
 
     // scratch for the per-check bookkeeping
     HIPCHK(S, dalloc(S, &S->st_dev, 1));
@@ -561,14 +568,11 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
         HIPCHK(S, hipFuncSetAttribute((const void *)k_persist, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)S->lds_persist));
     }
-    const int want = std::min(1024, std::max(64, (n * P + 63) / 64 * 64));
-    S->bt_persist = want;
-    while ((n + S->bt_persist - 1) / S->bt_persist > CHMAX && S->bt_persist < 1024) S->bt_persist += 64;
-    if ((n + S->bt_persist - 1) / S->bt_persist > CHMAX) S->persist_ok = 0;
+    S->bt_persist = std::min(1024, std::max(64, (n * P + 63) / 64 * 64));
 
     // initial velocities, copies into every replica, forces, Omega and the observable shift
     if (!D->vel) {
-        hipLaunchKernelGGL(k_init_vel, dim3((n + 255) / 256), dim3(256), 0, S->stream, S->d, (float)D->kT);
+        hipLaunchKernelGGL(k_init_vel, dim3((n + 255) / 256), dim3(256), 0, S->stream, S->d_dev, (float)D->kT);
         LAUNCHCHK(S);
     }
     gpr_status rc = launch_forces(S, 0, 1, -1, 1, 0, 1);
@@ -578,7 +582,7 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
     HIPCHK(S, hipMemsetAsync(d.need_build, 0, sizeof(int) * R, S->stream));
     rc = launch_forces(S, 0, R, -1, 1, 0, 1);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_obs, dim3(1), dim3(256), S->lds_stage, S->stream, S->d, 0, 1, nullptr);
+    hipLaunchKernelGGL(k_obs, dim3(1), dim3(256), S->lds_stage, S->stream, S->d_dev, 0, 1, nullptr);
     LAUNCHCHK(S);
     rc = state_of_ref(S, &S->omega);
     if (rc) return rc;
@@ -673,7 +677,6 @@ extern "C" gpr_status gpr_set_launch(gpr_system *S, int32_t block_threads, int32
     if (block_threads != 0) {
         if (block_threads < 64 || block_threads > 1024 || block_threads % 64)
             return fail(S, GPR_EINVAL, "block_threads must be a multiple of 64 in [64, 1024]");
-        if ((S->n + block_threads - 1) / block_threads > CHMAX) return fail(S, GPR_EINVAL, "block too small for the system");
         S->bt_persist = block_threads;
     }
     return GPR_OK;
@@ -796,9 +799,9 @@ extern "C" gpr_status gpr_observe(gpr_system *S, double *obs, int32_t *state)
         gpr_status rc = launch_forces(S, 0, S->R, -1, 1, 0, 1);
         if (rc) return rc;
     }
-    hipLaunchKernelGGL(k_obs, dim3(S->R), dim3(256), S->lds_stage, S->stream, S->d, 0, 2, S->obs_out);
+    hipLaunchKernelGGL(k_obs, dim3(S->R), dim3(256), S->lds_stage, S->stream, S->d_dev, 0, 2, S->obs_out);
     LAUNCHCHK(S);
-    hipLaunchKernelGGL(k_state, dim3(S->R), dim3(256), S->lds_stage, S->stream, S->d, 0);
+    hipLaunchKernelGGL(k_state, dim3(S->R), dim3(256), S->lds_stage, S->stream, S->d_dev, 0);
     LAUNCHCHK(S);
     std::vector<double> h((size_t)S->R * MAX_OBS);
     std::vector<int> st(S->R);
@@ -873,7 +876,7 @@ extern "C" gpr_status gpr_dephase(gpr_system *S, int64_t max_steps, gpr_dephase_
             rc = launch_forces(S, 0, 1, -1, 1, 0, 1);
             if (rc) return rc;
         }
-        hipLaunchKernelGGL(k_obs, dim3(1), dim3(256), S->lds_stage, S->stream, S->d, 0, 1, nullptr);
+        hipLaunchKernelGGL(k_obs, dim3(1), dim3(256), S->lds_stage, S->stream, S->d_dev, 0, 1, nullptr);
         LAUNCHCHK(S);
         S->nsamp = 0;
         S->dp_t = 0;

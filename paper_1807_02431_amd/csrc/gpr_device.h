@@ -4,10 +4,13 @@
 //   x, v      float  [R][3][np]   SoA per replica (coalesced per coordinate)
 //   F         int64  [R][3][np]   forces in 64-bit fixed point, 2^-32 kJ/mol/nm per unit
 //   xb        float  [R][3][np]   positions at the last pair-list build (displacement guard)
-//   nbl       uint16 [R][K][np*P] pair lists, slot-major: entry k of sub-list (i, q) at
-//                                 k*np*P + i*P + q, so the P lanes of consecutive atoms read
-//                                 consecutive halfwords
-//   nbc       uint16 [R][np*P]    sub-list lengths
+//   nbl       uint2  [R][Kg][np*P] pair lists in groups of four 16-bit partner indices,
+//                                 slot-major: group g of sub-list (i, q) at g*np*P + i*P + q,
+//                                 so the P lanes of consecutive atoms read consecutive 8-byte
+//                                 words; the last group is padded with the dummy atom n
+//   nbc       uint16 [R][np*P]    groups per sub-list
+// Atom n (np >= n + 1) is a dummy placed far away with zero parameters: a pair with it
+// contributes an exact zero.
 //   acc       double [R][MAX_OBS][2]  observable sums S1, S2 (Eq. 2-3)
 // Per-atom parameters (shared by all replicas): prm = (sigma/2, 2 sqrt(eps), q sqrt(f), 1/m).
 //
@@ -29,6 +32,7 @@ constexpr int BLK = 32;         // atoms per bounding sphere in the pair search
 constexpr double FIX = 4294967296.0;          // 2^32
 constexpr double FIX_INV = 2.3283064365386963e-10;  // 2^-32
 constexpr float FMAX_FIX = 1.0e9f;             // |F| beyond this counts as unstable
+constexpr float FAR = 1.0e15f;                 // coordinate of the dummy atom
 
 enum { KIND_TOY = 1, KIND_MOL = 2 };
 enum { ST_SIGN_X = 1, ST_BOXES = 2, ST_COM = 3 };
@@ -73,8 +77,9 @@ struct Dev {
     float *x, *v, *xb;
     long long *F;
     long long *E;                          // [R] potential energy, fixed point
-    unsigned short *nbl, *nbc;
-    int K;                                 // capacity of one sub-list
+    uint2 *nbl;
+    unsigned short *nbc;
+    int Kg;                                // capacity of one sub-list, in groups of four
     int *guard;                            // [2][R] displacement guard flags by step parity
     int *need_build;                       // [R]
     int *err;                              // [4] error flags
@@ -84,14 +89,37 @@ struct Dev {
     const int *groups;
     int nobs;
     int need_energy;                       // an observable is the potential energy
-    ObsDesc obs[MAX_OBS];
-    StateDesc st;
+    const ObsDesc *obs;                    // [MAX_OBS], device memory
+    const StateDesc *st;                   // device memory
     Topo tp;
     float h, c1, rc2, rl, rl2, krf, crf, half_skin2;
     int cutoff_on, period;
     uint32_t key0, key1;
     int t_gr;
 };
+
+// Pointers read from the device-resident descriptor are generic; casting them to the global
+// address space makes the compiler emit global (not flat) memory instructions, whose
+// completion is tracked apart from LDS traffic.
+#define GPR_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const GPR_GLOBAL T *gconst(const T *p) { return (const GPR_GLOBAL T *)p; }
+template <class T>
+__device__ __forceinline__ GPR_GLOBAL T *gmut(T *p) { return (GPR_GLOBAL T *)p; }
+
+// vector loads/stores through native vector types (HIP's vector classes cannot be copied
+// from an address-space-qualified reference)
+typedef int gv_i2 __attribute__((ext_vector_type(2)));
+typedef int gv_i4 __attribute__((ext_vector_type(4)));
+typedef unsigned gv_u2 __attribute__((ext_vector_type(2)));
+typedef float gv_f2 __attribute__((ext_vector_type(2)));
+typedef float gv_f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ int2 gld(const GPR_GLOBAL int2 *p) { const gv_i2 v = *(const GPR_GLOBAL gv_i2 *)p; return make_int2(v.x, v.y); }
+__device__ __forceinline__ int4 gld(const GPR_GLOBAL int4 *p) { const gv_i4 v = *(const GPR_GLOBAL gv_i4 *)p; return make_int4(v.x, v.y, v.z, v.w); }
+__device__ __forceinline__ uint2 gld(const GPR_GLOBAL uint2 *p) { const gv_u2 v = *(const GPR_GLOBAL gv_u2 *)p; return make_uint2(v.x, v.y); }
+__device__ __forceinline__ float2 gld(const GPR_GLOBAL float2 *p) { const gv_f2 v = *(const GPR_GLOBAL gv_f2 *)p; return make_float2(v.x, v.y); }
+__device__ __forceinline__ float4 gld(const GPR_GLOBAL float4 *p) { const gv_f4 v = *(const GPR_GLOBAL gv_f4 *)p; return make_float4(v.x, v.y, v.z, v.w); }
+__device__ __forceinline__ void gst(GPR_GLOBAL uint2 *p, uint2 v) { gv_u2 w; w.x = v.x; w.y = v.y; *(GPR_GLOBAL gv_u2 *)p = w; }
 
 // ------------------------------------------------------------------ Philox4x32-10
 // Salmon, Moraes, Dror, Shaw (SC'11): ten rounds; each multiplies words 0 and 2 by fixed

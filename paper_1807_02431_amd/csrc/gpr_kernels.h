@@ -18,16 +18,16 @@ struct Status {
     double rhat[MAX_OBS];
 };
 
-__global__ void k_integrate(Dev S, long long s, int r_off, int energy);
-__global__ void k_bonded(Dev S, int r_off, int energy);
-__global__ void k_nonbonded(Dev S, long long s, int r_off, int energy, int apply_b, int force_build);
-__global__ void k_obs(Dev S, int r_off, int mode, double *out);
-__global__ void k_state(Dev S, int r_off);
-__global__ void k_persist(Dev S, long long s0, int nsteps, int t0, int sample, int state_end);
-__global__ void k_check(Dev S, int mode, long long s, int omega, int nrep, long long nsamp, int check_index,
+__global__ void k_integrate(const Dev *__restrict__ Sp, long long s, int r_off, int energy);
+__global__ void k_bonded(const Dev *__restrict__ Sp, int r_off, int energy);
+__global__ void k_nonbonded(const Dev *__restrict__ Sp, long long s, int r_off, int energy, int apply_b, int force_build);
+__global__ void k_obs(const Dev *__restrict__ Sp, int r_off, int mode, double *out);
+__global__ void k_state(const Dev *__restrict__ Sp, int r_off);
+__global__ void k_persist(const Dev *__restrict__ Sp, long long s0, int nsteps, int t0, int sample, int state_end);
+__global__ void k_check(const Dev *__restrict__ Sp, int mode, long long s, int omega, int nrep, long long nsamp, int check_index,
                         Status *st, int *donor, int *surv, long long *fec);
-__global__ void k_clone(Dev S, const int *donor, int acc_mode);
-__global__ void k_init_vel(Dev S, float kT);
+__global__ void k_clone(const Dev *__restrict__ Sp, const int *donor, int acc_mode);
+__global__ void k_init_vel(const Dev *__restrict__ Sp, float kT);
 __global__ void k_noise_test(uint32_t k0, uint32_t k1, int replica, long long step, int stream, int n,
                              uint32_t *words, float *gauss);
 __global__ void k_fvplan_test(uint32_t k0, uint32_t k1, long long s, int R, const uint8_t *exited, int *donor, int *surv);

@@ -36,7 +36,7 @@ struct PosLDS {
     __device__ float3 operator()(int a) const { const float4 p = xs[a]; return make_float3(p.x, p.y, p.z); }
 };
 struct PosGlob {
-    const float *x;
+    const GPR_GLOBAL float *x;
     int np;
     __device__ float3 operator()(int a) const { return make_float3(x[a], x[np + a], x[2 * np + a]); }
 };
@@ -52,6 +52,11 @@ __device__ void bonded_range(const Dev &S, const Pos &pos, int a0, int a1, long 
                              long long *e_acc, int tid, int nthr)
 {
     const Topo &T = S.tp;
+    const GPR_GLOBAL int2 *b_ij = gconst(T.b_ij); const GPR_GLOBAL float2 *b_p = gconst(T.b_p);
+    const GPR_GLOBAL int4 *a_ijk = gconst(T.a_ijk); const GPR_GLOBAL float2 *a_p = gconst(T.a_p);
+    const GPR_GLOBAL int4 *t_ijkl = gconst(T.t_ijkl); const GPR_GLOBAL float4 *t_p = gconst(T.t_p);
+    const GPR_GLOBAL int *r_i = gconst(T.r_i); const GPR_GLOBAL float4 *r_p = gconst(T.r_p);
+    const GPR_GLOBAL int2 *p_ij = gconst(T.p_ij); const GPR_GLOBAL float4 *p_p = gconst(T.p_p);
     auto add = [&](int a, float3 f) {
         if (a >= a0 && a < a1) {
             lds_add(&fa[a - a0], fix_f(f.x));
@@ -61,11 +66,11 @@ __device__ void bonded_range(const Dev &S, const Pos &pos, int a0, int a1, long 
     };
     long long e = 0;
     if (T.nb) {
-        const int lo = T.b_start[max(0, a0 - T.b_span)], hi = T.b_start[a1];
+        const int lo = gconst(T.b_start)[max(0, a0 - T.b_span)], hi = gconst(T.b_start)[a1];
         for (int t = lo + tid; t < hi; t += nthr) {
-            const int2 ij = T.b_ij[t];
+            const int2 ij = gld(b_ij + t);
             float3 fi;
-            const float u = term_bond(pos(ij.x), pos(ij.y), T.b_p[t], fi);
+            const float u = term_bond(pos(ij.x), pos(ij.y), gld(b_p + t), fi);
             add(ij.x, fi);
             add(ij.y, neg3(fi));
             const int mn = min(ij.x, ij.y);
@@ -73,11 +78,11 @@ __device__ void bonded_range(const Dev &S, const Pos &pos, int a0, int a1, long 
         }
     }
     if (T.na) {
-        const int lo = T.a_start[max(0, a0 - T.a_span)], hi = T.a_start[a1];
+        const int lo = gconst(T.a_start)[max(0, a0 - T.a_span)], hi = gconst(T.a_start)[a1];
         for (int t = lo + tid; t < hi; t += nthr) {
-            const int4 q = T.a_ijk[t];
+            const int4 q = gld(a_ijk + t);
             float3 fi, fk;
-            const float u = term_angle(pos(q.x), pos(q.y), pos(q.z), T.a_p[t], fi, fk);
+            const float u = term_angle(pos(q.x), pos(q.y), pos(q.z), gld(a_p + t), fi, fk);
             add(q.x, fi);
             add(q.z, fk);
             add(q.y, make_float3(-fi.x - fk.x, -fi.y - fk.y, -fi.z - fk.z));
@@ -86,11 +91,11 @@ __device__ void bonded_range(const Dev &S, const Pos &pos, int a0, int a1, long 
         }
     }
     if (T.nt) {
-        const int lo = T.t_start[max(0, a0 - T.t_span)], hi = T.t_start[a1];
+        const int lo = gconst(T.t_start)[max(0, a0 - T.t_span)], hi = gconst(T.t_start)[a1];
         for (int t = lo + tid; t < hi; t += nthr) {
-            const int4 q = T.t_ijkl[t];
+            const int4 q = gld(t_ijkl + t);
             float3 fi, fj, fk, fl;
-            const float u = term_torsion(pos(q.x), pos(q.y), pos(q.z), pos(q.w), T.t_p[t], fi, fj, fk, fl);
+            const float u = term_torsion(pos(q.x), pos(q.y), pos(q.z), pos(q.w), gld(t_p + t), fi, fj, fk, fl);
             add(q.x, fi);
             add(q.y, fj);
             add(q.z, fk);
@@ -100,10 +105,10 @@ __device__ void bonded_range(const Dev &S, const Pos &pos, int a0, int a1, long 
         }
     }
     if (T.nr) {
-        const int lo = T.r_start[a0], hi = T.r_start[a1];
+        const int lo = gconst(T.r_start)[a0], hi = gconst(T.r_start)[a1];
         for (int t = lo + tid; t < hi; t += nthr) {
-            const int a = T.r_i[t];
-            const float4 p = T.r_p[t];
+            const int a = r_i[t];
+            const float4 p = gld(r_p + t);
             const float3 x = pos(a);
             const float dx = x.x - p.x, dy = x.y - p.y, dz = x.z - p.z;
             add(a, make_float3(-p.w * dx, -p.w * dy, -p.w * dz));
@@ -111,11 +116,11 @@ __device__ void bonded_range(const Dev &S, const Pos &pos, int a0, int a1, long 
         }
     }
     if (T.n14) {
-        const int lo = T.p_start[max(0, a0 - T.p_span)], hi = T.p_start[a1];
+        const int lo = gconst(T.p_start)[max(0, a0 - T.p_span)], hi = gconst(T.p_start)[a1];
         for (int t = lo + tid; t < hi; t += nthr) {
-            const int2 ij = T.p_ij[t];
+            const int2 ij = gld(p_ij + t);
             float3 fi;
-            const float u = term_pair14(pos(ij.x), pos(ij.y), T.p_p[t], fi);
+            const float u = term_pair14(pos(ij.x), pos(ij.y), gld(p_p + t), fi);
             add(ij.x, fi);
             add(ij.y, neg3(fi));
             const int mn = min(ij.x, ij.y);
@@ -155,15 +160,19 @@ __device__ void block_spheres(const Dev &S, const float4 *xs, float4 *sph, int t
 }
 
 // Sub-list (i, q): partners j = q (mod P), j != i, not excluded, |x_i - x_j| < r_list, in
-// ascending order.  allpairs: no distance test (vacuum systems without cutoff).
-__device__ void build_lane(const Dev &S, int r, int i, int q, const float4 *xs, const float4 *sph, bool allpairs)
+// ascending order, packed four to an 8-byte word and padded with the dummy atom.
+// allpairs: no distance test (vacuum systems without cutoff).
+__device__ __noinline__ void build_lane(const Dev &S, int r, int i, int q, const float4 *xs, const float4 *sph,
+                                        bool allpairs)
 {
     const size_t stride = (size_t)S.np * P;
-    unsigned short *L = S.nbl + (size_t)r * S.K * stride + (size_t)i * P + q;
+    GPR_GLOBAL uint2 *L = gmut(S.nbl) + (size_t)r * S.Kg * stride + (size_t)i * P + q;
     const float4 pi = xs[i];
-    const unsigned long long ex = S.excl[i];
+    const unsigned long long ex = gconst(S.excl)[i];
     const int nblk = (S.n + BLK - 1) / BLK;
-    int cnt = 0;
+    const uint32_t dummy = (uint32_t)S.n;
+    int cnt = 0, g = 0;
+    uint32_t w0 = 0, w1 = 0;
     bool over = false;
     for (int b = 0; b < nblk; ++b) {
         if (!allpairs) {
@@ -182,53 +191,94 @@ __device__ void build_lane(const Dev &S, int r, int i, int q, const float4 *xs, 
                 const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
                 if (dx * dx + dy * dy + dz * dz >= S.rl2) continue;
             }
-            if (cnt < S.K) L[(size_t)cnt * stride] = (unsigned short)j;
-            else over = true;
+            const int slot = cnt & 3;
+            if (slot == 0) w0 = (uint32_t)j;
+            else if (slot == 1) w0 |= (uint32_t)j << 16;
+            else if (slot == 2) w1 = (uint32_t)j;
+            else {
+                w1 |= (uint32_t)j << 16;
+                if (g < S.Kg) gst(L + (size_t)g * stride, make_uint2(w0, w1));
+                else over = true;
+                ++g;
+            }
             ++cnt;
         }
     }
-    S.nbc[(size_t)r * stride + (size_t)i * P + q] = (unsigned short)min(cnt, S.K);
+    const int slot = cnt & 3;
+    if (slot) {
+        if (slot == 1) w0 |= dummy << 16;
+        if (slot <= 2) w1 = dummy | (dummy << 16);
+        else w1 |= dummy << 16;
+        if (g < S.Kg) gst(L + (size_t)g * stride, make_uint2(w0, w1));
+        else over = true;
+        ++g;
+    }
+    gmut(S.nbc)[(size_t)r * stride + (size_t)i * P + q] = (unsigned short)min(g, S.Kg);
     if (over) atomicOr(&S.err[ERR_LIST], 1);
 }
 
 // ------------------------------------------------------------------ nonbonded partial sum of one lane
 // Lennard-Jones + Coulomb (vacuum when krf = crf = 0 and rc2 = inf; reaction field
-// otherwise) over sub-list (i, q); returns (F_x, F_y, F_z, U/2 summed over the partners).
+// otherwise) of one pair, accumulated into (fx, fy, fz) and, with energy, U/2 into e.
+__device__ __forceinline__ void pair_term(const float4 pi, const float2 ppi, const float4 pj, const float2 ppj,
+                                          float rc2, float krf2, float krf, float crf, bool energy,
+                                          float &fx, float &fy, float &fz, float &e)
+{
+    const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float r2i = ri * ri;
+    const float sg = ppi.x + ppj.x;
+    const float s2 = (sg * sg) * r2i;
+    const float s6 = (s2 * s2) * s2;
+    const float e4 = ppi.y * ppj.y;
+    const float qq = pi.w * pj.w;
+    // -dU/dr / r = e4 r2i (12 s6^2 - 6 s6) + qq (ri r2i - 2 krf)
+    const float lj = (e4 * r2i) * (s6 * fmaf(12.0f, s6, -6.0f));
+    const float fs0 = fmaf(qq, fmaf(ri, r2i, -krf2), lj);
+    const bool in = r2 < rc2;
+    const float fs = in ? fs0 : 0.0f;
+    fx = fmaf(fs, dx, fx);
+    fy = fmaf(fs, dy, fy);
+    fz = fmaf(fs, dz, fz);
+    if (energy) {
+        const float u = fmaf(e4 * s6, s6 - 1.0f, qq * (fmaf(krf, r2, ri) - crf));
+        e = in ? fmaf(0.5f, u, e) : e;
+    }
+}
+
+// Sum over sub-list (i, q), four partners per 8-byte list word, the next word loaded one
+// group ahead; returns (F_x, F_y, F_z, sum U/2).
+template <bool ENERGY>
+__device__ __forceinline__ float4 nb_lane_t(const Dev &S, int r, int i, int q, const float4 *xs, const float2 *pp)
+{
+    const size_t stride = (size_t)S.np * P;
+    const GPR_GLOBAL uint2 *L = gconst(S.nbl) + (size_t)r * S.Kg * stride + (size_t)i * P + q;
+    const int ng = gconst(S.nbc)[(size_t)r * stride + (size_t)i * P + q];
+    const float4 pi = xs[i];
+    const float2 ppi = pp[i];
+    const float rc2 = S.rc2, krf = S.krf, krf2 = 2.0f * S.krf, crf = S.crf;
+    float fx = 0.f, fy = 0.f, fz = 0.f, e = 0.f;
+    uint2 nxt = make_uint2(0u, 0u);
+    if (ng > 0) nxt = gld(L);
+    for (int g = 0; g < ng; ++g) {
+        const uint2 cur = nxt;
+        if (g + 1 < ng) nxt = gld(L + (size_t)(g + 1) * stride);
+        const int j0 = cur.x & 0xFFFF, j1 = cur.x >> 16, j2 = cur.y & 0xFFFF, j3 = cur.y >> 16;
+        const float4 x0 = xs[j0], x1 = xs[j1], x2 = xs[j2], x3 = xs[j3];
+        const float2 p0 = pp[j0], p1 = pp[j1], p2 = pp[j2], p3 = pp[j3];
+        pair_term(pi, ppi, x0, p0, rc2, krf2, krf, crf, ENERGY, fx, fy, fz, e);
+        pair_term(pi, ppi, x1, p1, rc2, krf2, krf, crf, ENERGY, fx, fy, fz, e);
+        pair_term(pi, ppi, x2, p2, rc2, krf2, krf, crf, ENERGY, fx, fy, fz, e);
+        pair_term(pi, ppi, x3, p3, rc2, krf2, krf, crf, ENERGY, fx, fy, fz, e);
+    }
+    return make_float4(fx, fy, fz, e);
+}
+
 __device__ __forceinline__ float4 nb_lane(const Dev &S, int r, int i, int q, const float4 *xs, const float2 *pp,
                                           bool energy)
 {
-    const size_t stride = (size_t)S.np * P;
-    const unsigned short *L = S.nbl + (size_t)r * S.K * stride + (size_t)i * P + q;
-    const int cnt = S.nbc[(size_t)r * stride + (size_t)i * P + q];
-    const float4 pi = xs[i];
-    const float2 ppi = pp[i];
-    const float rc2 = S.rc2, krf2 = 2.0f * S.krf;
-    float fx = 0.f, fy = 0.f, fz = 0.f, e = 0.f;
-    for (int k = 0; k < cnt; ++k) {
-        const int j = L[(size_t)k * stride];
-        const float4 pj = xs[j];
-        const float2 ppj = pp[j];
-        const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        const float ri = __builtin_amdgcn_rsqf(r2);
-        const float r2i = ri * ri;
-        const float sg = ppi.x + ppj.x;
-        const float s2 = sg * sg * r2i;
-        const float s6 = s2 * s2 * s2;
-        const float e4 = ppi.y * ppj.y;
-        const float qq = pi.w * pj.w;
-        float fs = e4 * r2i * (12.0f * s6 * s6 - 6.0f * s6) + qq * (ri * r2i - krf2);
-        const bool in = r2 < rc2;
-        fs = in ? fs : 0.0f;
-        fx += fs * dx;
-        fy += fs * dy;
-        fz += fs * dz;
-        if (energy) {
-            const float u = e4 * (s6 * s6 - s6) + qq * (ri + S.krf * r2 - S.crf);
-            e += in ? 0.5f * u : 0.0f;
-        }
-    }
-    return make_float4(fx, fy, fz, e);
+    return energy ? nb_lane_t<true>(S, r, i, q, xs, pp) : nb_lane_t<false>(S, r, i, q, xs, pp);
 }
 
 // ------------------------------------------------------------------ one B A O A for one atom
@@ -291,7 +341,7 @@ __device__ __forceinline__ double3 xs_d(const float4 *xs, int a)
 
 __device__ int state_wg(const Dev &S, const float4 *xs, long long *red, int *sbuf, int tid, int nthr)
 {
-    const StateDesc &st = S.st;
+    const StateDesc &st = *S.st;
     if (st.kind == ST_SIGN_X) return xs[st.atoms[0]].x >= 0.0f ? 1 : 0;
     if (st.kind == ST_BOXES) {
         if (tid == 0) {
@@ -329,6 +379,7 @@ __device__ void observables_wg(const Dev &S, const float4 *xs, const float *vg, 
 {
     if (tid < MAX_OBS * 8) red[tid] = 0;
     __syncthreads();
+#pragma unroll 1
     for (int j = 0; j < S.nobs; ++j) {
         const ObsDesc &o = S.obs[j];
         long long *dst = red + 8 * j;
@@ -352,6 +403,7 @@ __device__ void observables_wg(const Dev &S, const float4 *xs, const float *vg, 
     }
     __syncthreads();
     if (tid == 0) {
+#pragma unroll 1
         for (int j = 0; j < S.nobs; ++j) {
             const ObsDesc &o = S.obs[j];
             const long long *src = red + 8 * j;
@@ -396,19 +448,20 @@ __device__ __forceinline__ void accumulate_obs(const Dev &S, int r, const double
 // stage positions (x, y, z, q sqrt f) and (sigma/2, 2 sqrt eps) of replica r into LDS
 __device__ __forceinline__ void stage_replica(const Dev &S, int r, float4 *xs, float2 *pp, int tid, int nthr)
 {
-    const float *xg = S.x + (size_t)r * 3 * S.np;
+    const GPR_GLOBAL float *xg = gconst(S.x) + (size_t)r * 3 * S.np;
     for (int a = tid; a < S.np; a += nthr) {
-        const float4 pr = S.prm[a];
+        const float4 pr = gld(gconst(S.prm) + a);
         if (a < S.n) xs[a] = make_float4(xg[a], xg[S.np + a], xg[2 * S.np + a], pr.z);
-        else xs[a] = make_float4(0.f, 0.f, 0.f, 0.f);
+        else xs[a] = make_float4(FAR, FAR, FAR, 0.f);
         if (pp) pp[a] = make_float2(pr.x, pr.y);
     }
 }
 
 // ================================================================== plain path kernels
 // B A O A for every atom of replicas r_off + blockIdx.y; displacement guard; energy reset.
-__global__ void __launch_bounds__(256) k_integrate(Dev S, long long s, int r_off, int energy)
+__global__ void __launch_bounds__(256) k_integrate(const Dev *__restrict__ Sp, long long s, int r_off, int energy)
 {
+    const Dev &S = *Sp;
     const int r = r_off + blockIdx.y;
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     int *guard = S.guard + (s & 1) * S.R + r;
@@ -418,24 +471,29 @@ __global__ void __launch_bounds__(256) k_integrate(Dev S, long long s, int r_off
     }
     if (a >= S.n) return;
     const size_t b = (size_t)r * 3 * S.np;
-    float3 x = make_float3(S.x[b + a], S.x[b + S.np + a], S.x[b + 2 * S.np + a]);
-    float3 v = make_float3(S.v[b + a], S.v[b + S.np + a], S.v[b + 2 * S.np + a]);
-    const float3 F = make_float3(unfix_f(S.F[b + a]), unfix_f(S.F[b + S.np + a]), unfix_f(S.F[b + 2 * S.np + a]));
-    const float im = S.prm[a].w;
-    integrate_baoa(S, a, r, s, x, v, F, im, S.sd[a]);
-    S.x[b + a] = x.x; S.x[b + S.np + a] = x.y; S.x[b + 2 * S.np + a] = x.z;
-    S.v[b + a] = v.x; S.v[b + S.np + a] = v.y; S.v[b + 2 * S.np + a] = v.z;
+    const int np = S.np;
+    GPR_GLOBAL float *X = gmut(S.x) + b, *V = gmut(S.v) + b;
+    const GPR_GLOBAL float *XB = gconst(S.xb) + b;
+    const GPR_GLOBAL long long *Fp = gconst(S.F) + b;
+    float3 x = make_float3(X[a], X[np + a], X[2 * np + a]);
+    float3 v = make_float3(V[a], V[np + a], V[2 * np + a]);
+    const float3 F = make_float3(unfix_f(Fp[a]), unfix_f(Fp[np + a]), unfix_f(Fp[2 * np + a]));
+    const float im = gld(gconst(S.prm) + a).w;
+    integrate_baoa(S, a, r, s, x, v, F, im, gconst(S.sd)[a]);
+    X[a] = x.x; X[np + a] = x.y; X[2 * np + a] = x.z;
+    V[a] = v.x; V[np + a] = v.y; V[2 * np + a] = v.z;
     if (!finite3(x) || !finite3(v)) atomicOr(&S.err[ERR_UNSTABLE], 1);
     if (S.cutoff_on) {
-        const float dx = x.x - S.xb[b + a], dy = x.y - S.xb[b + S.np + a], dz = x.z - S.xb[b + 2 * S.np + a];
+        const float dx = x.x - XB[a], dy = x.y - XB[np + a], dz = x.z - XB[2 * np + a];
         if (!(dx * dx + dy * dy + dz * dz <= S.half_skin2)) atomicOr(guard, 1);
     }
 }
 
 // Bonded forces of atom range [blockIdx.x * blockDim.x, +blockDim.x) of replica r:
 // fixed-point LDS accumulation, then a plain store that initialises F for the step.
-__global__ void __launch_bounds__(256) k_bonded(Dev S, int r_off, int energy)
+__global__ void __launch_bounds__(256) k_bonded(const Dev *__restrict__ Sp, int r_off, int energy)
 {
+    const Dev &S = *Sp;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     long long *fa = (long long *)lds_raw;
     __shared__ long long e_acc;
@@ -456,7 +514,7 @@ __global__ void __launch_bounds__(256) k_bonded(Dev S, int r_off, int energy)
             if (energy) e_acc = fix_f(u);
         }
     } else {
-        bonded_range(S, PosGlob{S.x + b, S.np}, a0, a1, fa, len, energy ? &e_acc : nullptr, tid, len);
+        bonded_range(S, PosGlob{gconst(S.x) + b, S.np}, a0, a1, fa, len, energy ? &e_acc : nullptr, tid, len);
     }
     __syncthreads();
     const int a = a0 + tid;
@@ -471,9 +529,10 @@ __global__ void __launch_bounds__(256) k_bonded(Dev S, int r_off, int energy)
 // Nonbonded forces of atoms [blockIdx.x * blockDim.x / P, ...) of replica r (P lanes per
 // atom), added to the bonded forces; then the closing B kick (apply_b).  The pair lists of
 // the block's atoms are rebuilt first when due (period, displacement guard, force_build).
-__global__ void __launch_bounds__(256) k_nonbonded(Dev S, long long s, int r_off, int energy, int apply_b,
+__global__ void __launch_bounds__(1024) k_nonbonded(const Dev *__restrict__ Sp, long long s, int r_off, int energy, int apply_b,
                                                    int force_build)
 {
+    const Dev &S = *Sp;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     float4 *xs = (float4 *)lds_raw;
     float2 *pp = (float2 *)(xs + S.np);
@@ -511,17 +570,19 @@ __global__ void __launch_bounds__(256) k_nonbonded(Dev S, long long s, int r_off
         f.z = quad_sum(f.z);
         if (energy) f.w = quad_sum(f.w);
         if (q == 0) {
-            const long long Fx = S.F[b + i] + fix_f(f.x);
-            const long long Fy = S.F[b + S.np + i] + fix_f(f.y);
-            const long long Fz = S.F[b + 2 * S.np + i] + fix_f(f.z);
-            S.F[b + i] = Fx; S.F[b + S.np + i] = Fy; S.F[b + 2 * S.np + i] = Fz;
+            GPR_GLOBAL long long *Fp = gmut(S.F) + b;
+            GPR_GLOBAL float *V = gmut(S.v) + b;
+            const long long Fx = Fp[i] + fix_f(f.x);
+            const long long Fy = Fp[S.np + i] + fix_f(f.y);
+            const long long Fz = Fp[2 * S.np + i] + fix_f(f.z);
+            Fp[i] = Fx; Fp[S.np + i] = Fy; Fp[2 * S.np + i] = Fz;
             const float fx = unfix_f(Fx), fy = unfix_f(Fy), fz = unfix_f(Fz);
             if (bad_force(fx) || bad_force(fy) || bad_force(fz)) atomicOr(&S.err[ERR_UNSTABLE], 1);
             if (apply_b) {
-                const float im = S.prm[i].w, h = S.h;
-                S.v[b + i] = kick(S.v[b + i], fx, h, im);
-                S.v[b + S.np + i] = kick(S.v[b + S.np + i], fy, h, im);
-                S.v[b + 2 * S.np + i] = kick(S.v[b + 2 * S.np + i], fz, h, im);
+                const float im = gld(gconst(S.prm) + i).w, h = S.h;
+                V[i] = kick(V[i], fx, h, im);
+                V[S.np + i] = kick(V[S.np + i], fy, h, im);
+                V[2 * S.np + i] = kick(V[2 * S.np + i], fz, h, im);
             }
             if (energy) eatom = fix_f(f.w);
         }
@@ -536,8 +597,9 @@ __global__ void __launch_bounds__(256) k_nonbonded(Dev S, long long s, int r_off
 
 // observables of replicas r_off + blockIdx.x: accumulate (mode 0, workers), set the shift
 // c_j from replica 0 (mode 1), or write the values to out[r][MAX_OBS] (mode 2)
-__global__ void __launch_bounds__(256) k_obs(Dev S, int r_off, int mode, double *out)
+__global__ void __launch_bounds__(256) k_obs(const Dev *__restrict__ Sp, int r_off, int mode, double *out)
 {
+    const Dev &S = *Sp;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     float4 *xs = (float4 *)lds_raw;
     __shared__ long long red[MAX_OBS * 8 + 8];
@@ -555,8 +617,9 @@ __global__ void __launch_bounds__(256) k_obs(Dev S, int r_off, int mode, double 
 }
 
 // state ids of replicas r_off + blockIdx.x
-__global__ void __launch_bounds__(256) k_state(Dev S, int r_off)
+__global__ void __launch_bounds__(256) k_state(const Dev *__restrict__ Sp, int r_off)
 {
+    const Dev &S = *Sp;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     float4 *xs = (float4 *)lds_raw;
     __shared__ long long red[8];
@@ -569,16 +632,17 @@ __global__ void __launch_bounds__(256) k_state(Dev S, int r_off)
 }
 
 // ================================================================== persistent path
-// One workgroup per replica advances nsteps BAOAB steps.  LDS holds the replica's positions
-// (float4 with the scaled charge), the per-atom LJ parameters, the fixed-point force
-// accumulators, block spheres and reduction scratch; each thread keeps the velocities and
-// forces of up to CHMAX atoms (atoms tid, tid + BT, ...) in registers.  Per step:
-// B A O A (own atoms) -> pair-list rebuild when due -> bonded terms (LDS atomics) ->
-// pair forces (P lanes per atom) -> closing B; every t_GR steps (t counted from t0) the
-// observables of workers are accumulated.  With state_end the state id is written at the end.
-__global__ void __launch_bounds__(1024) k_persist(Dev S, long long s0, int nsteps, int t0, int sample,
+// One workgroup per replica advances nsteps BAOAB steps with the replica resident in LDS:
+// positions (float4 with the scaled charge), LJ parameters, velocities, fixed-point force
+// accumulators (which also carry the forces from one step to the next), block spheres and
+// reduction scratch.  Per step: B A O A (atoms tid, tid + BT, ...) -> pair-list rebuild
+// when due -> bonded terms (LDS atomics) -> pair forces (P lanes per atom) -> closing B;
+// every t_GR steps (t counted from t0) the observables of workers are accumulated.  With
+// state_end the state id is written at the end.
+__global__ void __launch_bounds__(1024) k_persist(const Dev *__restrict__ Sp, long long s0, int nsteps, int t0, int sample,
                                                   int state_end)
 {
+    const Dev &S = *Sp;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int np = S.np, n = S.n;
     long long *fa = (long long *)lds_raw;                 // [3][np]
@@ -586,32 +650,28 @@ __global__ void __launch_bounds__(1024) k_persist(Dev S, long long s0, int nstep
     double *vals = (double *)(red + MAX_OBS * 8 + 8);      // [MAX_OBS]
     float4 *xs = (float4 *)(vals + MAX_OBS);               // [np]
     float2 *pp = (float2 *)(xs + np);                      // [np]
-    float4 *sph = (float4 *)(pp + np);                     // [nblk]
+    float *vs = (float *)(pp + np);                        // [3][np]
+    float4 *sph = (float4 *)(vs + 3 * np);                 // [nblk]
     __shared__ int sbuf;
     const int r = blockIdx.x;
     const int tid = threadIdx.x, BT = blockDim.x;
     const size_t b = (size_t)r * 3 * np;
-    float *xg = S.x + b, *vg = S.v + b, *xbg = S.xb + b;
-    long long *Fg = S.F + b;
+    GPR_GLOBAL float *xg = gmut(S.x) + b, *xbg = gmut(S.xb) + b;
+    float *vg = S.v + b;
+    GPR_GLOBAL long long *Fg = gmut(S.F) + b;
+    const GPR_GLOBAL float4 *prm = gconst(S.prm);
+    const GPR_GLOBAL float *sdv = gconst(S.sd);
 
     stage_replica(S, r, xs, pp, tid, BT);
-    float vr[CHMAX][3], Fr[CHMAX][3], imr[CHMAX], sdr[CHMAX];
-#pragma unroll
-    for (int c = 0; c < CHMAX; ++c) {
-        const int a = c * BT + tid;
-        if (a < n) {
-            for (int d = 0; d < 3; ++d) { vr[c][d] = vg[d * np + a]; Fr[c][d] = unfix_f(Fg[d * np + a]); }
-            imr[c] = S.prm[a].w;
-            sdr[c] = S.sd[a];
-        } else {
-            for (int d = 0; d < 3; ++d) { vr[c][d] = 0.f; Fr[c][d] = 0.f; }
-            imr[c] = 0.f; sdr[c] = 0.f;
-        }
+    for (int k = tid; k < 3 * np; k += BT) {
+        vs[k] = gconst(vg)[k];
+        fa[k] = Fg[k];
     }
     bool need = S.need_build[r] != 0;
     __syncthreads();
     if (tid == 0) S.need_build[r] = 0;
     const bool toy = S.kind == KIND_TOY;
+    long long *eacc = red + MAX_OBS * 8;
 
     for (int step = 0; step < nsteps; ++step) {
         const long long s = s0 + step;
@@ -619,20 +679,17 @@ __global__ void __launch_bounds__(1024) k_persist(Dev S, long long s0, int nstep
         const bool samp = sample && r >= 1 && (tl % S.t_gr == 0);
         const bool energy = samp && S.need_energy;
         int hit = 0, bad = 0;
-#pragma unroll
-        for (int c = 0; c < CHMAX; ++c) {
-            const int a = c * BT + tid;
-            if (a < n) {
-                float3 x = make_float3(xs[a].x, xs[a].y, xs[a].z);
-                float3 v = make_float3(vr[c][0], vr[c][1], vr[c][2]);
-                integrate_baoa(S, a, r, s, x, v, make_float3(Fr[c][0], Fr[c][1], Fr[c][2]), imr[c], sdr[c]);
-                xs[a].x = x.x; xs[a].y = x.y; xs[a].z = x.z;
-                vr[c][0] = v.x; vr[c][1] = v.y; vr[c][2] = v.z;
-                bad |= !(finite3(x) && finite3(v));
-                if (S.cutoff_on) {
-                    const float dx = x.x - xbg[a], dy = x.y - xbg[np + a], dz = x.z - xbg[2 * np + a];
-                    hit |= !(dx * dx + dy * dy + dz * dz <= S.half_skin2);
-                }
+        for (int a = tid; a < n; a += BT) {
+            float3 x = make_float3(xs[a].x, xs[a].y, xs[a].z);
+            float3 v = make_float3(vs[a], vs[np + a], vs[2 * np + a]);
+            const float3 F = make_float3(unfix_f(fa[a]), unfix_f(fa[np + a]), unfix_f(fa[2 * np + a]));
+            integrate_baoa(S, a, r, s, x, v, F, gld(prm + a).w, sdv[a]);
+            xs[a].x = x.x; xs[a].y = x.y; xs[a].z = x.z;
+            vs[a] = v.x; vs[np + a] = v.y; vs[2 * np + a] = v.z;
+            bad |= !(finite3(x) && finite3(v));
+            if (S.cutoff_on) {
+                const float dx = x.x - xbg[a], dy = x.y - xbg[np + a], dz = x.z - xbg[2 * np + a];
+                hit |= !(dx * dx + dy * dy + dz * dz <= S.half_skin2);
             }
         }
         if (bad) atomicOr(&S.err[ERR_UNSTABLE], 1);
@@ -648,7 +705,7 @@ __global__ void __launch_bounds__(1024) k_persist(Dev S, long long s0, int nstep
             need = false;
         }
         for (int k = tid; k < 3 * np; k += BT) fa[k] = 0;
-        if (tid == 0) red[MAX_OBS * 8] = 0;
+        if (tid == 0) *eacc = 0;
         __syncthreads();
         if (toy) {
             if (tid == 0) {
@@ -656,10 +713,10 @@ __global__ void __launch_bounds__(1024) k_persist(Dev S, long long s0, int nstep
                 const float u = toy_force(xs[0].x, xs[0].y, fx, fy);
                 fa[0] = fix_f(fx);
                 fa[np] = fix_f(fy);
-                if (energy) red[MAX_OBS * 8] = fix_f(u);
+                if (energy) *eacc = fix_f(u);
             }
         } else {
-            bonded_range(S, PosLDS{xs}, 0, n, fa, np, energy ? &red[MAX_OBS * 8] : nullptr, tid, BT);
+            bonded_range(S, PosLDS{xs}, 0, n, fa, np, energy ? eacc : nullptr, tid, BT);
             for (int L0 = 0; L0 < n * P; L0 += BT) {
                 const int L = L0 + tid;
                 const int i = L / P, q = L % P;
@@ -679,43 +736,35 @@ __global__ void __launch_bounds__(1024) k_persist(Dev S, long long s0, int nstep
                 }
                 if (energy) {
                     eatom = wave_sum_ll(eatom);
-                    if ((tid & 63) == 0 && eatom != 0) lds_add(&red[MAX_OBS * 8], eatom);
+                    if ((tid & 63) == 0 && eatom != 0) lds_add(eacc, eatom);
                 }
             }
         }
         __syncthreads();
-#pragma unroll
-        for (int c = 0; c < CHMAX; ++c) {
-            const int a = c * BT + tid;
-            if (a < n) {
-                for (int d = 0; d < 3; ++d) {
-                    Fr[c][d] = unfix_f(fa[d * np + a]);
-                    vr[c][d] = kick(vr[c][d], Fr[c][d], S.h, imr[c]);
-                }
-                if (bad_force(Fr[c][0]) || bad_force(Fr[c][1]) || bad_force(Fr[c][2])) atomicOr(&S.err[ERR_UNSTABLE], 1);
-            }
+        for (int a = tid; a < n; a += BT) {
+            const float im = gld(prm + a).w, h = S.h;
+            const float Fx = unfix_f(fa[a]), Fy = unfix_f(fa[np + a]), Fz = unfix_f(fa[2 * np + a]);
+            vs[a] = kick(vs[a], Fx, h, im);
+            vs[np + a] = kick(vs[np + a], Fy, h, im);
+            vs[2 * np + a] = kick(vs[2 * np + a], Fz, h, im);
+            if (bad_force(Fx) || bad_force(Fy) || bad_force(Fz)) atomicOr(&S.err[ERR_UNSTABLE], 1);
         }
         if (samp) {
-#pragma unroll
-            for (int c = 0; c < CHMAX; ++c) {
-                const int a = c * BT + tid;
-                if (a < n) for (int d = 0; d < 3; ++d) vg[d * np + a] = vr[c][d];
-            }
             __syncthreads();
-            observables_wg(S, xs, vg, unfix_d(red[MAX_OBS * 8]), red, vals, tid, BT);
+            for (int k = tid; k < 3 * np; k += BT) gmut(vg)[k] = vs[k];
+            __syncthreads();
+            observables_wg(S, xs, vg, unfix_d(*eacc), red, vals, tid, BT);
             if (tid == 0) accumulate_obs(S, r, vals);
         }
         __syncthreads();
     }
     // write back the replica state
-#pragma unroll
-    for (int c = 0; c < CHMAX; ++c) {
-        const int a = c * BT + tid;
-        if (a < n) {
-            for (int d = 0; d < 3; ++d) vg[d * np + a] = vr[c][d];
-            xg[a] = xs[a].x; xg[np + a] = xs[a].y; xg[2 * np + a] = xs[a].z;
-            if (nsteps > 0) { Fg[a] = fa[a]; Fg[np + a] = fa[np + a]; Fg[2 * np + a] = fa[2 * np + a]; }
-        }
+    for (int a = tid; a < n; a += BT) {
+        xg[a] = xs[a].x; xg[np + a] = xs[a].y; xg[2 * np + a] = xs[a].z;
+    }
+    for (int k = tid; k < 3 * np; k += BT) {
+        gmut(vg)[k] = vs[k];
+        Fg[k] = fa[k];
     }
     if (state_end) {
         __syncthreads();
@@ -814,9 +863,10 @@ __device__ void vote_dev(int R, const long long *fec, long long t_check, long lo
 // CHK_DEPHASE (reference-exit test, branching plan into donor[], R-hat over workers with the
 // planned clones' sums), CHK_PARALLEL (first exiting replica), CHK_ADVANCE (record first
 // exit checks, R-hat computed and reported, nothing acted on).
-__global__ void __launch_bounds__(64) k_check(Dev S, int mode, long long s, int omega, int nrep, long long nsamp,
+__global__ void __launch_bounds__(64) k_check(const Dev *__restrict__ Sp, int mode, long long s, int omega, int nrep, long long nsamp,
                                               int check_index, Status *st, int *donor, int *surv, long long *fec)
 {
+    const Dev &S = *Sp;
     const int tid = threadIdx.x;
     __shared__ int no_surv;
     if (tid == 0) {
@@ -884,8 +934,9 @@ __global__ void __launch_bounds__(64) k_check(Dev S, int mode, long long s, int 
 // Copies (x, v, F) of replica donor[r] into replica r for every r with donor[r] >= 0 and
 // marks r for a pair-list rebuild; observable sums are copied too (acc_mode 1), or cleared
 // when the donor is the reference walker (a fresh broadcast).
-__global__ void __launch_bounds__(256) k_clone(Dev S, const int *donor, int acc_mode)
+__global__ void __launch_bounds__(256) k_clone(const Dev *__restrict__ Sp, const int *donor, int acc_mode)
 {
+    const Dev &S = *Sp;
     const int r = blockIdx.y;
     const int d = donor[r];
     if (d < 0 || d == r) return;
@@ -902,8 +953,9 @@ __global__ void __launch_bounds__(256) k_clone(Dev S, const int *donor, int acc_
 }
 
 // Maxwell-Boltzmann velocities of replica 0 (stream 1, step 0)
-__global__ void __launch_bounds__(256) k_init_vel(Dev S, float kT)
+__global__ void __launch_bounds__(256) k_init_vel(const Dev *__restrict__ Sp, float kT)
 {
+    const Dev &S = *Sp;
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= S.n) return;
     const float3 g = gauss3(philox_ctr((uint32_t)a, 0, 0u, STREAM_INIT, S.key0, S.key1));
