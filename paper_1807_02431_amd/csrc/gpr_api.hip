@@ -312,7 +312,7 @@ extern "C" const char *gpr_last_error(const gpr_system *S)
 
 static size_t persist_lds(int np)
 {
-    const int nblk = (np + BLK - 1) / BLK;
+    const int nblk = (np + BLK - 1) / BLK + (np + BLK2 - 1) / BLK2;
     return (size_t)3 * np * 8 + (MAX_OBS * 8 + 8) * 8 + MAX_OBS * 8 + (size_t)np * 16 + (size_t)np * 8 +
            (size_t)3 * np * 4 + (size_t)nblk * 16;
 }
@@ -551,7 +551,7 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
     HIPCHK(S, dalloc(S, &S->obs_out, (size_t)R * MAX_OBS));
 
     // LDS budgets
-    const int nblk = (n + BLK - 1) / BLK;
+    const int nblk = (n + BLK - 1) / BLK + (n + BLK2 - 1) / BLK2;
     S->lds_nb = (size_t)np * 24 + (size_t)nblk * 16;
     S->lds_stage = (size_t)np * 16;
     S->lds_persist = persist_lds(np);

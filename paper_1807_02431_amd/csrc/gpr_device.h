@@ -28,7 +28,8 @@ namespace gpr {
 constexpr int P = 4;            // lanes per atom in the pair loop (sub-lists by j mod P)
 constexpr int MAX_OBS = 8;
 constexpr int CHMAX = 4;        // atoms per thread in the integrator mapping
-constexpr int BLK = 32;         // atoms per bounding sphere in the pair search
+constexpr int BLK = 32;         // atoms per level-1 bounding sphere in the pair search
+constexpr int BLK2 = 8;         // atoms per level-2 bounding sphere (BLK2 a multiple of P)
 constexpr double FIX = 4294967296.0;          // 2^32
 constexpr double FIX_INV = 2.3283064365386963e-10;  // 2^-32
 constexpr float FMAX_FIX = 1.0e9f;             // |F| beyond this counts as unstable

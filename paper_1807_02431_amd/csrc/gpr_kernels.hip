@@ -140,12 +140,16 @@ __device__ __forceinline__ float toy_force(float x, float y, float &fx, float &f
 }
 
 // ------------------------------------------------------------------ pair search
-// Bounding spheres of the blocks of BLK consecutive atoms (chain-local, so compact).
-__device__ void block_spheres(const Dev &S, const float4 *xs, float4 *sph, int tid, int nthr)
+// Bounding spheres of blocks of consecutive atoms (chain-local, so compact): BLK atoms
+// (level 1) and BLK2 atoms (level 2).  Each radius is padded slightly so that rounding
+// cannot drop a pair.
+__device__ void block_spheres(const Dev &S, const float4 *xs, float4 *sph, float4 *sph2, int tid, int nthr)
 {
-    const int nblk = (S.n + BLK - 1) / BLK;
-    for (int b = tid; b < nblk; b += nthr) {
-        const int a0 = b * BLK, a1 = min(S.n, a0 + BLK);
+    const int nblk = (S.n + BLK - 1) / BLK, nblk2 = (S.n + BLK2 - 1) / BLK2;
+    for (int t = tid; t < nblk + nblk2; t += nthr) {
+        const bool l1 = t < nblk;
+        const int size = l1 ? BLK : BLK2;
+        const int a0 = (l1 ? t : t - nblk) * size, a1 = min(S.n, a0 + size);
         float cx = 0.f, cy = 0.f, cz = 0.f;
         for (int a = a0; a < a1; ++a) { cx += xs[a].x; cy += xs[a].y; cz += xs[a].z; }
         const float inv = 1.0f / (float)(a1 - a0);
@@ -155,66 +159,62 @@ __device__ void block_spheres(const Dev &S, const float4 *xs, float4 *sph, int t
             const float dx = xs[a].x - cx, dy = xs[a].y - cy, dz = xs[a].z - cz;
             r2 = fmaxf(r2, dx * dx + dy * dy + dz * dz);
         }
-        sph[b] = make_float4(cx, cy, cz, sqrtf(r2) * 1.0001f + 1e-6f);
+        const float4 c = make_float4(cx, cy, cz, sqrtf(r2) * 1.0001f + 1e-6f);
+        if (l1) sph[t] = c;
+        else sph2[t - nblk] = c;
     }
 }
 
+__device__ __forceinline__ bool sphere_near(const float4 pi, const float4 c, float rl)
+{
+    const float dx = pi.x - c.x, dy = pi.y - c.y, dz = pi.z - c.z;
+    const float lim = rl + c.w;
+    return dx * dx + dy * dy + dz * dz < lim * lim;
+}
+
 // Sub-list (i, q): partners j = q (mod P), j != i, not excluded, |x_i - x_j| < r_list, in
-// ascending order, packed four to an 8-byte word and padded with the dummy atom.
-// allpairs: no distance test (vacuum systems without cutoff).
+// ascending order; entry k is the 16-bit word k % 4 of group k / 4; the last group is
+// padded with the dummy atom.  Candidates come from the level-2 blocks inside level-1 blocks
+// whose spheres reach within r_list.  allpairs: no distance tests (vacuum, no cutoff).
 __device__ __noinline__ void build_lane(const Dev &S, int r, int i, int q, const float4 *xs, const float4 *sph,
-                                        bool allpairs)
+                                        const float4 *sph2, bool allpairs)
 {
     const size_t stride = (size_t)S.np * P;
-    GPR_GLOBAL uint2 *L = gmut(S.nbl) + (size_t)r * S.Kg * stride + (size_t)i * P + q;
+    GPR_GLOBAL unsigned short *L = (GPR_GLOBAL unsigned short *)(gmut(S.nbl) + (size_t)r * S.Kg * stride +
+                                                                   (size_t)i * P + q);
     const float4 pi = xs[i];
     const unsigned long long ex = gconst(S.excl)[i];
-    const int nblk = (S.n + BLK - 1) / BLK;
-    const uint32_t dummy = (uint32_t)S.n;
-    int cnt = 0, g = 0;
-    uint32_t w0 = 0, w1 = 0;
-    bool over = false;
+    const int nblk = (S.n + BLK - 1) / BLK, nblk2 = (S.n + BLK2 - 1) / BLK2;
+    const int cap = 4 * S.Kg;
+    const float rl = S.rl, rl2 = S.rl2;
+    int cnt = 0;
     for (int b = 0; b < nblk; ++b) {
-        if (!allpairs) {
-            const float4 c = sph[b];
-            const float dx = pi.x - c.x, dy = pi.y - c.y, dz = pi.z - c.z;
-            const float lim = S.rl + c.w;
-            if (dx * dx + dy * dy + dz * dz >= lim * lim) continue;
-        }
-        const int jend = min(S.n, (b + 1) * BLK);
-        for (int j = b * BLK + q; j < jend; j += P) {
-            if (j == i) continue;
-            const int off = j - i;
-            if (off >= -32 && off < 32 && ((ex >> (off + 32)) & 1ull)) continue;
-            if (!allpairs) {
-                const float4 pj = xs[j];
-                const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-                if (dx * dx + dy * dy + dz * dz >= S.rl2) continue;
+        if (!allpairs && !sphere_near(pi, sph[b], rl)) continue;
+        for (int b2 = b * (BLK / BLK2); b2 < min(nblk2, (b + 1) * (BLK / BLK2)); ++b2) {
+            if (!allpairs && !sphere_near(pi, sph2[b2], rl)) continue;
+#pragma unroll
+            for (int t = 0; t < BLK2 / P; ++t) {
+                const int j = b2 * BLK2 + q + t * P;
+                const int off = j - i;
+                const bool excl = off >= -32 && off < 32 && ((ex >> (off + 32)) & 1ull);
+                bool take = j < S.n && j != i && !excl;
+                if (!allpairs && take) {
+                    const float4 pj = xs[j];
+                    const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+                    take = fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < rl2;
+                }
+                if (take) {
+                    if (cnt < cap) L[((size_t)(cnt >> 2) * stride) * 4 + (cnt & 3)] = (unsigned short)j;
+                    ++cnt;
+                }
             }
-            const int slot = cnt & 3;
-            if (slot == 0) w0 = (uint32_t)j;
-            else if (slot == 1) w0 |= (uint32_t)j << 16;
-            else if (slot == 2) w1 = (uint32_t)j;
-            else {
-                w1 |= (uint32_t)j << 16;
-                if (g < S.Kg) gst(L + (size_t)g * stride, make_uint2(w0, w1));
-                else over = true;
-                ++g;
-            }
-            ++cnt;
         }
     }
-    const int slot = cnt & 3;
-    if (slot) {
-        if (slot == 1) w0 |= dummy << 16;
-        if (slot <= 2) w1 = dummy | (dummy << 16);
-        else w1 |= dummy << 16;
-        if (g < S.Kg) gst(L + (size_t)g * stride, make_uint2(w0, w1));
-        else over = true;
-        ++g;
-    }
-    gmut(S.nbc)[(size_t)r * stride + (size_t)i * P + q] = (unsigned short)min(g, S.Kg);
-    if (over) atomicOr(&S.err[ERR_LIST], 1);
+    const int ng = (cnt + 3) >> 2;
+    for (int k = cnt; k < 4 * ng; ++k)
+        if (k < cap) L[((size_t)(k >> 2) * stride) * 4 + (k & 3)] = (unsigned short)S.n;
+    gmut(S.nbc)[(size_t)r * stride + (size_t)i * P + q] = (unsigned short)min(ng, S.Kg);
+    if (cnt > cap) atomicOr(&S.err[ERR_LIST], 1);
 }
 
 // ------------------------------------------------------------------ nonbonded partial sum of one lane
@@ -537,6 +537,7 @@ __global__ void __launch_bounds__(1024) k_nonbonded(const Dev *__restrict__ Sp, 
     float4 *xs = (float4 *)lds_raw;
     float2 *pp = (float2 *)(xs + S.np);
     float4 *sph = (float4 *)(pp + S.np);
+    float4 *sph2 = sph + (S.n + BLK - 1) / BLK;
     __shared__ long long e_acc;
     const int r = r_off + blockIdx.y;
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -552,10 +553,10 @@ __global__ void __launch_bounds__(1024) k_nonbonded(const Dev *__restrict__ Sp, 
     const int q = tid % P;
     const size_t b = (size_t)r * 3 * S.np;
     if (rebuild) {
-        block_spheres(S, xs, sph, tid, nthr);
+        block_spheres(S, xs, sph, sph2, tid, nthr);
         __syncthreads();
         if (i < S.n) {
-            build_lane(S, r, i, q, xs, sph, !S.cutoff_on);
+            build_lane(S, r, i, q, xs, sph, sph2, !S.cutoff_on);
             if (q == 0) {
                 S.xb[b + i] = xs[i].x; S.xb[b + S.np + i] = xs[i].y; S.xb[b + 2 * S.np + i] = xs[i].z;
             }
@@ -652,6 +653,7 @@ __global__ void __launch_bounds__(1024) k_persist(const Dev *__restrict__ Sp, lo
     float2 *pp = (float2 *)(xs + np);                      // [np]
     float *vs = (float *)(pp + np);                        // [3][np]
     float4 *sph = (float4 *)(vs + 3 * np);                 // [nblk]
+    float4 *sph2 = sph + (n + BLK - 1) / BLK;              // [nblk2]
     __shared__ int sbuf;
     const int r = blockIdx.x;
     const int tid = threadIdx.x, BT = blockDim.x;
@@ -695,11 +697,11 @@ __global__ void __launch_bounds__(1024) k_persist(const Dev *__restrict__ Sp, lo
         if (bad) atomicOr(&S.err[ERR_UNSTABLE], 1);
         const int any_hit = __syncthreads_or(hit);
         if (S.cutoff_on && (need || any_hit || ((s + 1) % S.period == 0))) {
-            block_spheres(S, xs, sph, tid, BT);
+            block_spheres(S, xs, sph, sph2, tid, BT);
             __syncthreads();
             for (int L = tid; L < n * P; L += BT) {
                 const int i = L / P, q = L % P;
-                build_lane(S, r, i, q, xs, sph, false);
+                build_lane(S, r, i, q, xs, sph, sph2, false);
                 if (q == 0) { xbg[i] = xs[i].x; xbg[np + i] = xs[i].y; xbg[2 * np + i] = xs[i].z; }
             }
             need = false;
