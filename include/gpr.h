@@ -207,8 +207,10 @@ gpr_status gpr_set_stream(gpr_system *sys, void *hip_stream);
 #define GPR_PATH_PERSISTENT 1
 gpr_status gpr_set_path(gpr_system *sys, int32_t path);
 /* Launch shape of the persistent path: threads per workgroup (multiple of 64, <= 1024) and
- * workgroups per replica (1, 2, 4 or 8).  0 keeps the current value.  Results do not
- * depend on the shape. */
+ * workgroups per replica (1, 2, 4 or 8; a replica's atoms are split between its workgroups,
+ * which exchange positions every step).  0 keeps the current value.  EINVAL if the replicas
+ * times the workgroups per replica do not fit on the device at once.  Results do not depend
+ * on the shape. */
 gpr_status gpr_set_launch(gpr_system *sys, int32_t block_threads, int32_t groups_per_replica);
 
 /* ---------------------------------------------------------------- force field (Sec. 3.2) */

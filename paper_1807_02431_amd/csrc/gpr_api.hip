@@ -35,6 +35,8 @@ struct gpr_system {
     hipStream_t stream = nullptr;
     int path = GPR_PATH_PLAIN;
     int bt_persist = 0;
+    int groups = 1;            // workgroups per replica on the persistent path
+    int max_coresident = 0;    // persistent-kernel workgroups that fit on the device at once
     int n = 0, R = 0, np = 0, kind = 0, nobs = 0;
     int t_gr = 1, tcd = 1, tcp = 1;
     double tol = 0, dt = 0, kT = 0;
@@ -175,6 +177,17 @@ static hipError_t prof_collect(gpr_system *S)
     return hipSuccess;
 }
 
+// atoms owned by one group when a replica is split over G workgroups (as in k_persist)
+static int group_chunk(int n, int np, int G) { return G == 1 ? np : ((n + G - 1) / G + 15) / 16 * 16; }
+
+static size_t persist_lds(int n, int np, int G)
+{
+    const int lmax = group_chunk(n, np, G);
+    const int nblk = (n + BLK - 1) / BLK + (n + BLK2 - 1) / BLK2;
+    return (size_t)3 * lmax * 8 + (MAX_OBS * 8 + 8) * 8 + MAX_OBS * 8 + (size_t)np * 16 + (size_t)np * 8 +
+           (size_t)3 * lmax * 4 + (size_t)nblk * 16;
+}
+
 // ------------------------------------------------------------------ launches
 // forces of replicas [r_off, r_off + nrep) at their current positions.  Stepping calls
 // (force_build = 0) rely on k_integrate to clear the energies and maintain the list guard;
@@ -210,13 +223,27 @@ static gpr_status run_steps(gpr_system *S, int nrep, long long nsteps, long long
     }
     if (S->path == GPR_PATH_PERSISTENT) {
         long long done = 0;
+        const int G = S->groups;
+        const size_t lds = persist_lds(S->n, S->np, G);
         while (done < nsteps) {
             const int chunk = (int)std::min<long long>(nsteps - done, 1 << 20);
             const bool last = done + chunk == nsteps;
+            long long s0 = S->s + done;
+            int steps = chunk, tstart = (int)(t0 + done), samp = sample ? 1 : 0, send = (state_end && last) ? 1 : 0;
+            int g_ = G, nrep_ = nrep;
+            if (G > 1) HIPCHK(S, hipMemsetAsync(S->d.sync, 0, sizeof(int) * 64 * S->R, S->stream));
             HIPCHK(S, prof_begin(S));
-            hipLaunchKernelGGL(k_persist, dim3(nrep), dim3(S->bt_persist), S->lds_persist, S->stream, S->d_dev,
-                               S->s + done, chunk, (int)(t0 + done), sample ? 1 : 0, (state_end && last) ? 1 : 0);
-            LAUNCHCHK(S);
+            if (G == 1) {
+                hipLaunchKernelGGL(k_persist, dim3(nrep), dim3(S->bt_persist), lds, S->stream, S->d_dev, s0, steps,
+                                   tstart, samp, send, g_, nrep_);
+                LAUNCHCHK(S);
+            } else {
+                // all groups of a replica must be resident together: cooperative launch
+                const Dev *dp = S->d_dev;
+                void *args[] = {(void *)&dp, &s0, &steps, &tstart, &samp, &send, &g_, &nrep_};
+                HIPCHK(S, hipLaunchCooperativeKernel((const void *)k_persist, dim3(nrep * G), dim3(S->bt_persist), args,
+                                                     (unsigned)lds, S->stream));
+            }
             HIPCHK(S, prof_end(S));
             done += chunk;
         }
@@ -260,6 +287,7 @@ static gpr_status check(gpr_system *S, int mode, int nrep, int check_index)
     HIPCHK(S, prof_collect(S));
     if (S->st_host->err[ERR_UNSTABLE]) return fail(S, GPR_EUNSTABLE, "non-finite or overflowing state");
     if (S->st_host->err[ERR_LIST]) return fail(S, GPR_EDEVICE, "pair-list capacity exceeded");
+    if (S->st_host->err[ERR_BARRIER]) return fail(S, GPR_EDEVICE, "persistent-kernel barrier timed out");
     return GPR_OK;
 }
 
@@ -310,12 +338,6 @@ extern "C" const char *gpr_last_error(const gpr_system *S)
     return S ? S->err.c_str() : g_thread_err.c_str();
 }
 
-static size_t persist_lds(int np)
-{
-    const int nblk = (np + BLK - 1) / BLK + (np + BLK2 - 1) / BLK2;
-    return (size_t)3 * np * 8 + (MAX_OBS * 8 + 8) * 8 + MAX_OBS * 8 + (size_t)np * 16 + (size_t)np * 8 +
-           (size_t)3 * np * 4 + (size_t)nblk * 16;
-}
 
 static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
 {
@@ -496,6 +518,9 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
     HIPCHK(S, dalloc(S, &d.guard, 2 * R));
     HIPCHK(S, dalloc(S, &d.need_build, R));
     HIPCHK(S, dalloc(S, &d.err, 4));
+    HIPCHK(S, dalloc(S, &d.sync, (size_t)R * 64));
+    HIPCHK(S, dalloc(S, &d.xchg, (size_t)R * 3 * np));
+    HIPCHK(S, dalloc(S, &d.esum, R));
     HIPCHK(S, dalloc(S, &d.acc, (size_t)R * MAX_OBS * 2));
     HIPCHK(S, dalloc(S, &d.shift, MAX_OBS));
     HIPCHK(S, dalloc(S, &d.state, R));
@@ -554,7 +579,7 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
     const int nblk = (n + BLK - 1) / BLK + (n + BLK2 - 1) / BLK2;
     S->lds_nb = (size_t)np * 24 + (size_t)nblk * 16;
     S->lds_stage = (size_t)np * 16;
-    S->lds_persist = persist_lds(np);
+    S->lds_persist = persist_lds(n, np, 1);
     int dev = 0, maxlds = 0;
     HIPCHK(S, hipGetDevice(&dev));
     HIPCHK(S, hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -569,6 +594,21 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
                                       (int)S->lds_persist));
     }
     S->bt_persist = std::min(1024, std::max(64, (n * P + 63) / 64 * 64));
+    if (S->persist_ok) {
+        // default split: a power of two up to 8 workgroups per replica, each owning >= 256
+        // atoms, with every workgroup of the grid resident at once
+        int cus = 0, per_cu = 0;
+        HIPCHK(S, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        int G = 1;
+        while (G < 8 && (n + 2 * G - 1) / (2 * G) >= 256) {
+            HIPCHK(S, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_persist, S->bt_persist,
+                                                                  persist_lds(n, np, 2 * G)));
+            if ((long)R * 2 * G > (long)per_cu * cus) break;
+            G *= 2;
+        }
+        S->groups = G;
+        S->max_coresident = cus;
+    }
 
     // initial velocities, copies into every replica, forces, Omega and the observable shift
     if (!D->vel) {
@@ -673,12 +713,24 @@ extern "C" gpr_status gpr_set_path(gpr_system *S, int32_t path)
 extern "C" gpr_status gpr_set_launch(gpr_system *S, int32_t block_threads, int32_t groups_per_replica)
 {
     if (!S) return fail(nullptr, GPR_EINVAL, "NULL system");
-    if (groups_per_replica != 0 && groups_per_replica != 1) return fail(S, GPR_EINVAL, "groups_per_replica must be 1");
+    if (groups_per_replica != 0 && groups_per_replica != 1 && groups_per_replica != 2 && groups_per_replica != 4 &&
+        groups_per_replica != 8)
+        return fail(S, GPR_EINVAL, "groups_per_replica must be 1, 2, 4 or 8");
     if (block_threads != 0) {
         if (block_threads < 64 || block_threads > 1024 || block_threads % 64)
             return fail(S, GPR_EINVAL, "block_threads must be a multiple of 64 in [64, 1024]");
         S->bt_persist = block_threads;
     }
+    if (groups_per_replica > 1) {
+        int dev = 0, cus = 0, per_cu = 0;
+        HIPCHK(S, hipGetDevice(&dev));
+        HIPCHK(S, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        HIPCHK(S, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_persist, S->bt_persist,
+                                                              persist_lds(S->n, S->np, groups_per_replica)));
+        if ((long)S->R * groups_per_replica > (long)per_cu * cus)
+            return fail(S, GPR_EINVAL, "replicas x groups exceed the workgroups the device holds at once");
+    }
+    if (groups_per_replica != 0) S->groups = groups_per_replica;
     return GPR_OK;
 }
 
@@ -981,6 +1033,7 @@ extern "C" gpr_status gpr_advance(gpr_system *S, int64_t nsteps, int64_t *first_
     HIPCHK(S, prof_collect(S));
     if (err[ERR_UNSTABLE]) return fail(S, GPR_EUNSTABLE, "non-finite or overflowing state");
     if (err[ERR_LIST]) return fail(S, GPR_EDEVICE, "pair-list capacity exceeded");
+    if (err[ERR_BARRIER]) return fail(S, GPR_EDEVICE, "persistent-kernel barrier timed out");
     if (first_exit_check) for (int r = 0; r < S->R; ++r) first_exit_check[r] = f[r];
     return GPR_OK;
 }

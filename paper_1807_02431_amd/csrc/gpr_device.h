@@ -34,6 +34,7 @@ constexpr double FIX = 4294967296.0;          // 2^32
 constexpr double FIX_INV = 2.3283064365386963e-10;  // 2^-32
 constexpr float FMAX_FIX = 1.0e9f;             // |F| beyond this counts as unstable
 constexpr float FAR = 1.0e15f;                 // coordinate of the dummy atom
+constexpr int SPIN_MAX = 1 << 22;              // bound on a barrier wait (then ERR_BARRIER)
 
 enum { KIND_TOY = 1, KIND_MOL = 2 };
 enum { ST_SIGN_X = 1, ST_BOXES = 2, ST_COM = 3 };
@@ -84,6 +85,9 @@ struct Dev {
     int *guard;                            // [2][R] displacement guard flags by step parity
     int *need_build;                       // [R]
     int *err;                              // [4] error flags
+    int *sync;                             // [R][64] per-replica barrier counter and flags (groups > 1)
+    float *xchg;                           // [R][3][np] position exchange between a replica's groups
+    long long *esum;                       // [R] energy partial sums of a replica's groups
     double *acc;                           // [R][MAX_OBS][2]
     double *shift;                         // [MAX_OBS]
     int *state;                            // [R]

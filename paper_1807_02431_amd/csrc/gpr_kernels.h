@@ -23,7 +23,8 @@ __global__ void k_bonded(const Dev *__restrict__ Sp, int r_off, int energy);
 __global__ void k_nonbonded(const Dev *__restrict__ Sp, long long s, int r_off, int energy, int apply_b, int force_build);
 __global__ void k_obs(const Dev *__restrict__ Sp, int r_off, int mode, double *out);
 __global__ void k_state(const Dev *__restrict__ Sp, int r_off);
-__global__ void k_persist(const Dev *__restrict__ Sp, long long s0, int nsteps, int t0, int sample, int state_end);
+__global__ void k_persist(const Dev *__restrict__ Sp, long long s0, int nsteps, int t0, int sample, int state_end,
+                          int G, int nrep);
 __global__ void k_check(const Dev *__restrict__ Sp, int mode, long long s, int omega, int nrep, long long nsamp, int check_index,
                         Status *st, int *donor, int *surv, long long *fec);
 __global__ void k_clone(const Dev *__restrict__ Sp, const int *donor, int acc_mode);

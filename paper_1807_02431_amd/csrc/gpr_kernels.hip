@@ -306,8 +306,14 @@ __device__ __forceinline__ bool finite3(float3 a) { return isfinite(a.x) && isfi
 // ------------------------------------------------------------------ states and observables (FP64)
 // Workgroup-collective.  Sums over atoms are taken in 2^-32 fixed point so that they do
 // not depend on the launch shape.  red: LDS int64 scratch [MAX_OBS * 8 + 8].
+// velocity component load; coh: device-coherent load of values another workgroup wrote
+__device__ __forceinline__ float ldv(const float *p, bool coh)
+{
+    return coh ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *p;
+}
+
 __device__ void group_sum_wg(const Dev &S, const float4 *xs, const float *vg, int off, int cnt, int what,
-                             long long *dst, int tid, int nthr)
+                             long long *dst, int tid, int nthr, bool coh = false)
 {
     // what: 0 -> sum m x (3 slots), 1 -> sum |v|^2 (1 slot)
     for (int base = 0; base < cnt; base += nthr) {
@@ -321,7 +327,7 @@ __device__ void group_sum_wg(const Dev &S, const float4 *xs, const float *vg, in
                 s1 = fix_d(m * (double)xs[a].y);
                 s2 = fix_d(m * (double)xs[a].z);
             } else {
-                const double vx = vg[a], vy = vg[S.np + a], vz = vg[2 * S.np + a];
+                const double vx = ldv(vg + a, coh), vy = ldv(vg + S.np + a, coh), vz = ldv(vg + 2 * S.np + a, coh);
                 s0 = fix_d(vx * vx + vy * vy + vz * vz);
             }
         }
@@ -375,7 +381,7 @@ __device__ int state_wg(const Dev &S, const float4 *xs, long long *red, int *sbu
 
 // observable values into out[MAX_OBS] (LDS), valid after return
 __device__ void observables_wg(const Dev &S, const float4 *xs, const float *vg, double U, long long *red,
-                               double *out, int tid, int nthr)
+                               double *out, int tid, int nthr, bool coh = false)
 {
     if (tid < MAX_OBS * 8) red[tid] = 0;
     __syncthreads();
@@ -388,7 +394,7 @@ __device__ void observables_wg(const Dev &S, const float4 *xs, const float *vg, 
                 const int a = base + tid;
                 long long s = 0;
                 if (a < S.n) {
-                    const double vx = vg[a], vy = vg[S.np + a], vz = vg[2 * S.np + a];
+                    const double vx = ldv(vg + a, coh), vy = ldv(vg + S.np + a, coh), vz = ldv(vg + 2 * S.np + a, coh);
                     s = fix_d(0.5 * (double)S.mass[a] * (vx * vx + vy * vy + vz * vz));
                 }
                 s = wave_sum_ll(s);
@@ -398,7 +404,7 @@ __device__ void observables_wg(const Dev &S, const float4 *xs, const float *vg, 
             group_sum_wg(S, xs, vg, o.ga_off, o.ga_n, 0, dst, tid, nthr);
             group_sum_wg(S, xs, vg, o.gb_off, o.gb_n, 0, dst + 3, tid, nthr);
         } else if (o.kind == OB_RMSV) {
-            group_sum_wg(S, xs, vg, o.ga_off, o.ga_n, 1, dst, tid, nthr);
+            group_sum_wg(S, xs, vg, o.ga_off, o.ga_n, 1, dst, tid, nthr, coh);
         }
     }
     __syncthreads();
@@ -633,29 +639,78 @@ __global__ void __launch_bounds__(256) k_state(const Dev *__restrict__ Sp, int r
 }
 
 // ================================================================== persistent path
-// One workgroup per replica advances nsteps BAOAB steps with the replica resident in LDS:
-// positions (float4 with the scaled charge), LJ parameters, velocities, fixed-point force
-// accumulators (which also carry the forces from one step to the next), block spheres and
-// reduction scratch.  Per step: B A O A (atoms tid, tid + BT, ...) -> pair-list rebuild
-// when due -> bonded terms (LDS atomics) -> pair forces (P lanes per atom) -> closing B;
-// every t_GR steps (t counted from t0) the observables of workers are accumulated.  With
-// state_end the state id is written at the end.
-__global__ void __launch_bounds__(1024) k_persist(const Dev *__restrict__ Sp, long long s0, int nsteps, int t0, int sample,
-                                                  int state_end)
+// Barrier among the G workgroups of one replica: every thread waits for its own global
+// stores to complete, then one thread adds to the replica's counter (device-scope relaxed
+// atomic) and waits, with a bounded spin, for all G arrivals of this generation.  Data
+// exchanged between the groups is written and read with device-scope relaxed atomics, so
+// no cache writeback or invalidation is needed.  Returns false after a timeout.
+__device__ __forceinline__ bool group_barrier(int *ctr, int target, int *err, int *sbuf)
+{
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int spins = 0, ok = 1;
+        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++spins > SPIN_MAX) {
+                atomicOr(err + ERR_BARRIER, 1);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        *sbuf = ok;
+    }
+    __syncthreads();
+    const bool ok = *sbuf != 0;
+    __syncthreads();
+    return ok;
+}
+
+__device__ __forceinline__ void st_coh(float *p, float v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ __forceinline__ float ld_coh(const float *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+// G workgroups per replica advance nsteps BAOAB steps.  Group g of replica r owns the atoms
+// [a0, a1) (chunk = ceil(n / G) rounded to 16); its LDS holds the positions (float4 with the
+// scaled charge) and LJ parameters of every atom of the replica, and the velocities and
+// fixed-point force accumulators of its own atoms (the accumulators carry the forces from one
+// step to the next), block spheres and reduction scratch.  Per step: B A O A of own atoms ->
+// (G > 1) positions exchanged through device-coherent stores, barrier -> pair-list rebuild of
+// own atoms when due -> bonded terms touching own atoms (LDS atomics) -> pair forces of own
+// atoms (P lanes per atom) -> closing B; every t_GR steps (t counted from t0) the observables
+// of workers are accumulated by group 0.  With state_end group 0 writes the state id.
+// Workgroups map to replicas so that a replica's groups share an XCD (blockIdx mod 8) when the
+// replica count allows; results do not depend on G or the block size.
+__global__ void __launch_bounds__(1024) k_persist(const Dev *__restrict__ Sp, long long s0, int nsteps, int t0,
+                                                  int sample, int state_end, int G, int nrep)
 {
     const Dev &S = *Sp;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int np = S.np, n = S.n;
-    long long *fa = (long long *)lds_raw;                 // [3][np]
-    long long *red = fa + 3 * np;                          // [MAX_OBS * 8 + 8]
+    const int chunk = G == 1 ? np : ((n + G - 1) / G + 15) / 16 * 16;
+    const int lmax = chunk;
+    long long *fa = (long long *)lds_raw;                 // [3][lmax]
+    long long *red = fa + 3 * lmax;                        // [MAX_OBS * 8 + 8]
     double *vals = (double *)(red + MAX_OBS * 8 + 8);      // [MAX_OBS]
     float4 *xs = (float4 *)(vals + MAX_OBS);               // [np]
     float2 *pp = (float2 *)(xs + np);                      // [np]
-    float *vs = (float *)(pp + np);                        // [3][np]
-    float4 *sph = (float4 *)(vs + 3 * np);                 // [nblk]
+    float *vs = (float *)(pp + np);                        // [3][lmax]
+    float4 *sph = (float4 *)(vs + 3 * lmax);               // [nblk]
     float4 *sph2 = sph + (n + BLK - 1) / BLK;              // [nblk2]
-    __shared__ int sbuf;
-    const int r = blockIdx.x;
+    __shared__ int sbuf, bbuf, hbuf;
+
+    int r, g;
+    if (G == 1) {
+        r = blockIdx.x; g = 0;
+    } else if (nrep % 8 == 0) {
+        const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
+        r = (slot / G) * 8 + xcd;
+        g = slot % G;
+    } else {
+        r = blockIdx.x / G; g = blockIdx.x % G;
+    }
+    if (r >= nrep) return;
+    const int a0 = min(n, g * chunk), a1 = min(n, a0 + chunk);
     const int tid = threadIdx.x, BT = blockDim.x;
     const size_t b = (size_t)r * 3 * np;
     GPR_GLOBAL float *xg = gmut(S.x) + b, *xbg = gmut(S.xb) + b;
@@ -663,31 +718,37 @@ __global__ void __launch_bounds__(1024) k_persist(const Dev *__restrict__ Sp, lo
     GPR_GLOBAL long long *Fg = gmut(S.F) + b;
     const GPR_GLOBAL float4 *prm = gconst(S.prm);
     const GPR_GLOBAL float *sdv = gconst(S.sd);
+    int *sync = S.sync + (size_t)r * 64;
+    float *xch = S.xchg + b;
+    int gen = 0;
 
     stage_replica(S, r, xs, pp, tid, BT);
-    for (int k = tid; k < 3 * np; k += BT) {
-        vs[k] = gconst(vg)[k];
-        fa[k] = Fg[k];
+    for (int k = tid; k < 3 * lmax; k += BT) {
+        const int d = k / lmax, a = a0 + k % lmax;
+        vs[k] = a < a1 ? gconst(vg)[d * np + a] : 0.f;
+        fa[k] = a < a1 ? Fg[d * np + a] : 0;
     }
     bool need = S.need_build[r] != 0;
     __syncthreads();
-    if (tid == 0) S.need_build[r] = 0;
     const bool toy = S.kind == KIND_TOY;
     long long *eacc = red + MAX_OBS * 8;
+    bool alive = true;
 
-    for (int step = 0; step < nsteps; ++step) {
+    for (int step = 0; step < nsteps && alive; ++step) {
         const long long s = s0 + step;
         const int tl = t0 + step + 1;
         const bool samp = sample && r >= 1 && (tl % S.t_gr == 0);
         const bool energy = samp && S.need_energy;
         int hit = 0, bad = 0;
-        for (int a = tid; a < n; a += BT) {
+        for (int a = a0 + tid; a < a1; a += BT) {
+            const int l = a - a0;
             float3 x = make_float3(xs[a].x, xs[a].y, xs[a].z);
-            float3 v = make_float3(vs[a], vs[np + a], vs[2 * np + a]);
-            const float3 F = make_float3(unfix_f(fa[a]), unfix_f(fa[np + a]), unfix_f(fa[2 * np + a]));
+            float3 v = make_float3(vs[l], vs[lmax + l], vs[2 * lmax + l]);
+            const float3 F = make_float3(unfix_f(fa[l]), unfix_f(fa[lmax + l]), unfix_f(fa[2 * lmax + l]));
             integrate_baoa(S, a, r, s, x, v, F, gld(prm + a).w, sdv[a]);
             xs[a].x = x.x; xs[a].y = x.y; xs[a].z = x.z;
-            vs[a] = v.x; vs[np + a] = v.y; vs[2 * np + a] = v.z;
+            vs[l] = v.x; vs[lmax + l] = v.y; vs[2 * lmax + l] = v.z;
+            if (G > 1) { st_coh(xch + a, x.x); st_coh(xch + np + a, x.y); st_coh(xch + 2 * np + a, x.z); }
             bad |= !(finite3(x) && finite3(v));
             if (S.cutoff_on) {
                 const float dx = x.x - xbg[a], dy = x.y - xbg[np + a], dz = x.z - xbg[2 * np + a];
@@ -695,44 +756,61 @@ __global__ void __launch_bounds__(1024) k_persist(const Dev *__restrict__ Sp, lo
             }
         }
         if (bad) atomicOr(&S.err[ERR_UNSTABLE], 1);
-        const int any_hit = __syncthreads_or(hit);
+        int any_hit;
+        if (G > 1) {
+            // displacement-guard flags in three rotating slots; group 0 clears the slot of the next step
+            if (hit) __hip_atomic_fetch_or(sync + 16 + 16 * (int)(s % 3), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (g == 0 && tid == 0) __hip_atomic_store(sync + 16 + 16 * (int)((s + 1) % 3), 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            alive = group_barrier(sync, G * ++gen, S.err, &bbuf);
+            if (!alive) break;
+            if (tid == 0) hbuf = __hip_atomic_load(sync + 16 + 16 * (int)(s % 3), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int a = tid; a < n; a += BT) {
+                if (a >= a0 && a < a1) continue;
+                xs[a].x = ld_coh(xch + a); xs[a].y = ld_coh(xch + np + a); xs[a].z = ld_coh(xch + 2 * np + a);
+            }
+            __syncthreads();
+            any_hit = hbuf;
+        } else {
+            any_hit = __syncthreads_or(hit);
+        }
         if (S.cutoff_on && (need || any_hit || ((s + 1) % S.period == 0))) {
             block_spheres(S, xs, sph, sph2, tid, BT);
             __syncthreads();
-            for (int L = tid; L < n * P; L += BT) {
+            for (int L = a0 * P + tid; L < a1 * P; L += BT) {
                 const int i = L / P, q = L % P;
                 build_lane(S, r, i, q, xs, sph, sph2, false);
                 if (q == 0) { xbg[i] = xs[i].x; xbg[np + i] = xs[i].y; xbg[2 * np + i] = xs[i].z; }
             }
             need = false;
         }
-        for (int k = tid; k < 3 * np; k += BT) fa[k] = 0;
+        for (int k = tid; k < 3 * lmax; k += BT) fa[k] = 0;
         if (tid == 0) *eacc = 0;
         __syncthreads();
         if (toy) {
-            if (tid == 0) {
+            if (tid == 0 && a0 == 0 && a1 > 0) {
                 float fx, fy;
                 const float u = toy_force(xs[0].x, xs[0].y, fx, fy);
                 fa[0] = fix_f(fx);
-                fa[np] = fix_f(fy);
+                fa[lmax] = fix_f(fy);
                 if (energy) *eacc = fix_f(u);
             }
         } else {
-            bonded_range(S, PosLDS{xs}, 0, n, fa, np, energy ? eacc : nullptr, tid, BT);
-            for (int L0 = 0; L0 < n * P; L0 += BT) {
+            bonded_range(S, PosLDS{xs}, a0, a1, fa, lmax, energy ? eacc : nullptr, tid, BT);
+            for (int L0 = a0 * P; L0 < a1 * P; L0 += BT) {
                 const int L = L0 + tid;
                 const int i = L / P, q = L % P;
                 long long eatom = 0;
-                if (L < n * P) {
+                if (L < a1 * P) {
                     float4 f = nb_lane(S, r, i, q, xs, pp, energy);
                     f.x = quad_sum(f.x);
                     f.y = quad_sum(f.y);
                     f.z = quad_sum(f.z);
                     if (energy) f.w = quad_sum(f.w);
                     if (q == 0) {
-                        lds_add(&fa[i], fix_f(f.x));
-                        lds_add(&fa[np + i], fix_f(f.y));
-                        lds_add(&fa[2 * np + i], fix_f(f.z));
+                        const int l = i - a0;
+                        lds_add(&fa[l], fix_f(f.x));
+                        lds_add(&fa[lmax + l], fix_f(f.y));
+                        lds_add(&fa[2 * lmax + l], fix_f(f.z));
                         if (energy) eatom = fix_f(f.w);
                     }
                 }
@@ -743,32 +821,57 @@ __global__ void __launch_bounds__(1024) k_persist(const Dev *__restrict__ Sp, lo
             }
         }
         __syncthreads();
-        for (int a = tid; a < n; a += BT) {
+        for (int a = a0 + tid; a < a1; a += BT) {
+            const int l = a - a0;
             const float im = gld(prm + a).w, h = S.h;
-            const float Fx = unfix_f(fa[a]), Fy = unfix_f(fa[np + a]), Fz = unfix_f(fa[2 * np + a]);
-            vs[a] = kick(vs[a], Fx, h, im);
-            vs[np + a] = kick(vs[np + a], Fy, h, im);
-            vs[2 * np + a] = kick(vs[2 * np + a], Fz, h, im);
+            const float Fx = unfix_f(fa[l]), Fy = unfix_f(fa[lmax + l]), Fz = unfix_f(fa[2 * lmax + l]);
+            vs[l] = kick(vs[l], Fx, h, im);
+            vs[lmax + l] = kick(vs[lmax + l], Fy, h, im);
+            vs[2 * lmax + l] = kick(vs[2 * lmax + l], Fz, h, im);
             if (bad_force(Fx) || bad_force(Fy) || bad_force(Fz)) atomicOr(&S.err[ERR_UNSTABLE], 1);
         }
         if (samp) {
             __syncthreads();
-            for (int k = tid; k < 3 * np; k += BT) gmut(vg)[k] = vs[k];
-            __syncthreads();
-            observables_wg(S, xs, vg, unfix_d(*eacc), red, vals, tid, BT);
-            if (tid == 0) accumulate_obs(S, r, vals);
+            if (G == 1) {
+                for (int k = tid; k < 3 * np; k += BT) gmut(vg)[k] = k % np < n ? vs[(k / np) * lmax + k % np] : 0.f;
+                __syncthreads();
+                observables_wg(S, xs, vg, unfix_d(*eacc), red, vals, tid, BT);
+                if (tid == 0) accumulate_obs(S, r, vals);
+            } else {
+                // own velocities and energy to the group 0 of the replica
+                for (int a = a0 + tid; a < a1; a += BT) {
+                    const int l = a - a0;
+                    st_coh(vg + a, vs[l]); st_coh(vg + np + a, vs[lmax + l]); st_coh(vg + 2 * np + a, vs[2 * lmax + l]);
+                }
+                if (tid == 0 && energy && *eacc != 0)
+                    __hip_atomic_fetch_add(S.esum + r, *eacc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                alive = group_barrier(sync, G * ++gen, S.err, &bbuf);
+                if (!alive) break;
+                if (g == 0) {
+                    __shared__ long long etot;
+                    if (tid == 0) {
+                        etot = __hip_atomic_load(S.esum + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(S.esum + r, 0ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    __syncthreads();
+                    observables_wg(S, xs, vg, unfix_d(etot), red, vals, tid, BT, true);
+                    if (tid == 0) accumulate_obs(S, r, vals);
+                }
+            }
         }
         __syncthreads();
     }
-    // write back the replica state
-    for (int a = tid; a < n; a += BT) {
+    // write back this group's atoms
+    for (int a = a0 + tid; a < a1; a += BT) {
+        const int l = a - a0;
         xg[a] = xs[a].x; xg[np + a] = xs[a].y; xg[2 * np + a] = xs[a].z;
+        for (int d = 0; d < 3; ++d) {
+            gmut(vg)[d * np + a] = vs[d * lmax + l];
+            Fg[d * np + a] = fa[d * lmax + l];
+        }
     }
-    for (int k = tid; k < 3 * np; k += BT) {
-        gmut(vg)[k] = vs[k];
-        Fg[k] = fa[k];
-    }
-    if (state_end) {
+    if (g == 0 && tid == 0 && nsteps > 0) S.need_build[r] = 0;
+    if (state_end && g == 0) {
         __syncthreads();
         const int id = state_wg(S, xs, red, &sbuf, tid, BT);
         if (tid == 0) S.state[r] = id;

@@ -155,15 +155,16 @@ def test_positions_100_steps_full_size_sampled(path):
 
 def test_plain_and_persistent_paths_bit_identical():
     """Same arithmetic on both paths, fixed-point force accumulation, sub-lists in index
-    order: identical bits, across pair-list rebuilds, launch shapes and repeated runs."""
+    order: identical bits, across pair-list rebuilds, launch shapes (block size, replica split
+    over 1, 2 or 4 workgroups) and repeated runs."""
     gpr = _gpr()
     spec = G.config("rl300", n_replicas=8)
     say("bit identity rl300")
     runs = []
-    for path, bt in ((0, 0), (1, 0), (1, 320), (1, 1024), (0, 0)):
+    for path, bt, groups in ((0, 0, 0), (1, 0, 1), (1, 320, 1), (1, 1024, 1), (1, 0, 2), (1, 256, 4), (0, 0, 0)):
         s = gpr.System(spec, path=path)
-        if bt:
-            s.set_launch(bt, 0)
+        if bt or groups:
+            s.set_launch(bt, groups)
         s.advance(120)
         q = np.stack([s.get_state(r)[0] for r in range(8)])
         v = np.stack([s.get_state(r)[1] for r in range(8)])
