@@ -56,6 +56,37 @@ def in_cutoff_pairs(spec, q):
     return total
 
 
+def kernel_source_hash():
+    import hashlib
+    import glob
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1807_02431_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(steps_per_launch):
+    """HBM bytes per launch of the persistent kernel from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, or None when the kernel sources or the launch length differ from the
+    ones the counters were taken on."""
+    path = os.path.join(ROOT, "profiles", "k_persist_rl2432x64_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            parts = line.split()
+            if len(parts) == 2:
+                kv[parts[0]] = parts[1]
+    try:
+        ok = kv["source_sha256"] == kernel_source_hash() and int(kv["steps_per_launch"]) == int(round(steps_per_launch))
+        return int(kv["hbm_bytes_per_launch"]) if ok else None
+    except (KeyError, ValueError):
+        return None
+
+
 def flops_per_replica_step(spec, pairs):
     return (pairs * FLOP_PAIR + len(spec["bonds"]) * FLOP_BOND + len(spec["angles"]) * FLOP_ANGLE
             + len(spec["torsions"]) * FLOP_TORSION + len(spec["restraints"]) * FLOP_RESTRAINT
@@ -96,6 +127,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 256 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the replicas of one system share one device "
@@ -104,6 +137,14 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_probe:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": src.numel() * 4, "copy_probe_bytes_written": dst.numel() * 4}))
+        return
     import gpr_synth as G
     import paper_1807_02431_amd as gpr
 
@@ -165,7 +206,7 @@ def main():
                                "cutoff 1.0 nm reaction field, BAOAB dt 1 fs, t_GR 50, t_check 1000",
                    "n_atoms": n, "n_replicas": R, "path": "persistent"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(steps_per_launch),
                      "kernel": "k_persist", "avg_launch_us": avg_launch_s * 1e6,
                      "steps_per_launch": steps_per_launch, "flop_per_replica_step": frs,
                      "in_cutoff_pairs_per_replica": pairs},
