@@ -90,7 +90,7 @@ typedef struct gpr_obs_desc {
  * Force field (molecular kind):
  *   bond      1/2 k (r - r0)^2
  *   angle     1/2 k (theta - theta0)^2
- *   torsion   k (1 + cos(n phi - phi0)), phi the IUPAC dihedral (trans = pi)
+ *   torsion   k (1 + cos(n phi - phi0)), phi the IUPAC dihedral (trans = pi), integer n in [0, 12]
  *   restraint 1/2 k |r - r_ref|^2
  *   nonbonded, every pair that is neither excluded nor listed as a 1-4 pair:
  *     Lennard-Jones 4 eps_ij ((s_ij/r)^12 - (s_ij/r)^6), s_ij = (s_i+s_j)/2, eps_ij = sqrt(eps_i eps_j)
@@ -202,15 +202,18 @@ gpr_status gpr_set_stream(gpr_system *sys, void *hip_stream);
 
 /* Stepping path: GPR_PATH_PLAIN launches separate kernels every step (list build every
  * nlist_period, BAOAB, bonded, nonbonded); GPR_PATH_PERSISTENT advances whole check
- * periods in one launch with the replica state held on chip.  Results are bit-identical. */
+ * periods in one launch with the replica state held on chip.  Results are bit-identical.
+ * EINVAL for the persistent path when no split of a replica over 1, 2, 4 or 8 workgroups fits
+ * the device. */
 #define GPR_PATH_PLAIN      0
 #define GPR_PATH_PERSISTENT 1
 gpr_status gpr_set_path(gpr_system *sys, int32_t path);
 /* Launch shape of the persistent path: threads per workgroup (multiple of 64, <= 1024) and
  * workgroups per replica (1, 2, 4 or 8; a replica's atoms are split between its workgroups,
- * which exchange positions every step).  0 keeps the current value.  EINVAL if the replicas
- * times the workgroups per replica do not fit on the device at once.  Results do not depend
- * on the shape. */
+ * which exchange positions every step).  0 keeps the current value.  EINVAL, with nothing
+ * changed, if one workgroup's share of a replica does not fit in LDS (large systems need
+ * several workgroups per replica) or if the replicas times the workgroups per replica do not
+ * fit on the device at once.  Results do not depend on the shape. */
 gpr_status gpr_set_launch(gpr_system *sys, int32_t block_threads, int32_t groups_per_replica);
 
 /* ---------------------------------------------------------------- force field (Sec. 3.2) */

@@ -36,6 +36,8 @@ struct gpr_system {
     int path = GPR_PATH_PLAIN;
     int bt_persist = 0;
     int groups = 1;            // workgroups per replica on the persistent path
+    Split split{};             // their atom ranges
+    std::vector<double> work;  // per-atom work estimate that places the ranges
     int max_coresident = 0;    // persistent-kernel workgroups that fit on the device at once
     int n = 0, R = 0, np = 0, kind = 0, nobs = 0;
     int t_gr = 1, tcd = 1, tcp = 1;
@@ -54,6 +56,8 @@ struct gpr_system {
     int *donor = nullptr, *surv = nullptr;
     long long *fec = nullptr;
     size_t lds_persist = 0, lds_nb = 0, lds_stage = 0;
+    int maxlds = 0;            // LDS bytes one workgroup may use on this device
+    int maxlds_persist = 0;    // of which k_persist may allocate dynamically
     int persist_ok = 0;
     // event timing of the dominant stepping kernel
     bool prof = false;
@@ -177,15 +181,40 @@ static hipError_t prof_collect(gpr_system *S)
     return hipSuccess;
 }
 
-// atoms owned by one group when a replica is split over G workgroups (as in k_persist)
-static int group_chunk(int n, int np, int G) { return G == 1 ? np : ((n + G - 1) / G + 15) / 16 * 16; }
-
-static size_t persist_lds(int n, int np, int G)
+// Atom ranges of the G workgroups of a replica (k_persist): contiguous, starting at multiples
+// of 16 (so that every wave of the pair loop covers 16 atoms of one group), with boundaries
+// placed where the running sum of the per-atom work estimate crosses g/G of the total.
+static Split make_split(const std::vector<double> &work, int n, int np, int G)
 {
-    const int lmax = group_chunk(n, np, G);
-    const int nblk = (n + BLK - 1) / BLK + (n + BLK2 - 1) / BLK2;
+    Split sp{};
+    sp.G = G;
+    sp.bnd[0] = 0;
+    sp.bnd[G] = n;
+    if (G == 1) {
+        sp.lmax = np;
+        return sp;
+    }
+    std::vector<double> cum(n + 1, 0.0);
+    for (int i = 0; i < n; ++i) cum[i + 1] = cum[i] + work[i];
+    for (int g = 1; g < G; ++g) {
+        const double target = cum[n] * g / G;
+        int a = (int)(std::lower_bound(cum.begin(), cum.end(), target) - cum.begin());
+        const int lo = a / 16 * 16, hi = std::min(n, lo + 16);
+        a = (target - cum[lo] <= cum[hi] - target) ? lo : hi;
+        sp.bnd[g] = std::min(n, std::max(a, sp.bnd[g - 1]));
+    }
+    int lmax = 16;
+    for (int g = 0; g < G; ++g) lmax = std::max(lmax, sp.bnd[g + 1] - sp.bnd[g]);
+    sp.lmax = (lmax + 15) / 16 * 16;
+    return sp;
+}
+
+static size_t persist_lds(int n, int np, const Split &sp)
+{
+    const int lmax = sp.lmax;
+    const int nblk = (n + BLK - 1) / BLK;
     return (size_t)3 * lmax * 8 + (MAX_OBS * 8 + 8) * 8 + MAX_OBS * 8 + (size_t)np * 16 + (size_t)np * 8 +
-           (size_t)3 * lmax * 4 + (size_t)nblk * 16;
+           (size_t)8 * lmax * 4 + (size_t)nblk * 16;
 }
 
 // ------------------------------------------------------------------ launches
@@ -224,23 +253,25 @@ static gpr_status run_steps(gpr_system *S, int nrep, long long nsteps, long long
     if (S->path == GPR_PATH_PERSISTENT) {
         long long done = 0;
         const int G = S->groups;
-        const size_t lds = persist_lds(S->n, S->np, G);
+        const Split sp = S->split;
+        const size_t lds = persist_lds(S->n, S->np, sp);
         while (done < nsteps) {
             const int chunk = (int)std::min<long long>(nsteps - done, 1 << 20);
             const bool last = done + chunk == nsteps;
             long long s0 = S->s + done;
             int steps = chunk, tstart = (int)(t0 + done), samp = sample ? 1 : 0, send = (state_end && last) ? 1 : 0;
-            int g_ = G, nrep_ = nrep;
+            int nrep_ = nrep;
+            Split sp_ = sp;
             if (G > 1) HIPCHK(S, hipMemsetAsync(S->d.sync, 0, sizeof(int) * 64 * S->R, S->stream));
             HIPCHK(S, prof_begin(S));
             if (G == 1) {
                 hipLaunchKernelGGL(k_persist, dim3(nrep), dim3(S->bt_persist), lds, S->stream, S->d_dev, s0, steps,
-                                   tstart, samp, send, g_, nrep_);
+                                   tstart, samp, send, sp_, nrep_);
                 LAUNCHCHK(S);
             } else {
                 // all groups of a replica must be resident together: cooperative launch
                 const Dev *dp = S->d_dev;
-                void *args[] = {(void *)&dp, &s0, &steps, &tstart, &samp, &send, &g_, &nrep_};
+                void *args[] = {(void *)&dp, &s0, &steps, &tstart, &samp, &send, &sp_, &nrep_};
                 HIPCHK(S, hipLaunchCooperativeKernel((const void *)k_persist, dim3(nrep * G), dim3(S->bt_persist), args,
                                                      (unsigned)lds, S->stream));
             }
@@ -442,7 +473,8 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
                 const int t = order[k];
                 q[k] = make_int4(D->torsion_atoms[4 * t], D->torsion_atoms[4 * t + 1], D->torsion_atoms[4 * t + 2],
                                  D->torsion_atoms[4 * t + 3]);
-                p[k] = make_float4((float)D->torsion_k[t], (float)D->torsion_phi0[t], (float)D->torsion_n[t], 0.f);
+                p[k] = make_float4((float)D->torsion_k[t], (float)std::cos(D->torsion_phi0[t]),
+                                   (float)std::sin(D->torsion_phi0[t]), (float)D->torsion_n[t]);
             }
             T.nt = D->n_torsions;
             HIPCHK(S, upload(S, (int4 **)&T.t_ijkl, q)); HIPCHK(S, upload(S, (float4 **)&T.t_p, p));
@@ -497,18 +529,26 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
         d.half_skin2 = INFINITY; d.period = 1 << 30;
     }
     // capacity from the initial structure: the largest sub-list within r_list, doubled
+    // per-atom work estimate for the persistent split: partners within r_list plus a constant
+    // for the bonded terms and the integrator (about 32 pair evaluations' worth per atom)
     int maxsub = 0;
+    S->work.assign(n, 1.0);
     if (D->kind == GPR_KIND_MOLECULAR) {
         const double rl2 = d.cutoff_on ? (double)d.rl * d.rl * 1.21 : INFINITY;
+        const double rl2w = d.cutoff_on ? (double)d.rl * d.rl : INFINITY;
         std::vector<int> cnt(P);
         for (int i = 0; i < n; ++i) {
             std::fill(cnt.begin(), cnt.end(), 0);
+            int nw = 0;
             for (int j = 0; j < n; ++j) {
                 if (j == i) continue;
                 const double dx = D->pos[i] - D->pos[j], dy = D->pos[n + i] - D->pos[n + j], dz = D->pos[2 * n + i] - D->pos[2 * n + j];
-                if (dx * dx + dy * dy + dz * dz < rl2) cnt[j % P]++;
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 < rl2) cnt[j % P]++;
+                if (r2 < rl2w) nw++;
             }
             for (int q = 0; q < P; ++q) maxsub = std::max(maxsub, cnt[q]);
+            S->work[i] = nw + 32.0;
         }
     }
     const int kmax = std::max(8, d.cutoff_on ? 2 * maxsub + 8 : maxsub + 1);
@@ -576,38 +616,65 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
     HIPCHK(S, dalloc(S, &S->obs_out, (size_t)R * MAX_OBS));
 
     // LDS budgets
-    const int nblk = (n + BLK - 1) / BLK + (n + BLK2 - 1) / BLK2;
+    const int nblk = (n + BLK - 1) / BLK;
     S->lds_nb = (size_t)np * 24 + (size_t)nblk * 16;
     S->lds_stage = (size_t)np * 16;
-    S->lds_persist = persist_lds(n, np, 1);
     int dev = 0, maxlds = 0;
     HIPCHK(S, hipGetDevice(&dev));
     HIPCHK(S, hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    S->maxlds = maxlds;
     if ((int)S->lds_nb > maxlds || (int)S->lds_stage > maxlds)
         return fail(S, GPR_EINVAL, "system too large for the LDS-staged pair kernel");
     HIPCHK(S, hipFuncSetAttribute((const void *)k_nonbonded, hipFuncAttributeMaxDynamicSharedMemorySize, (int)S->lds_nb));
     HIPCHK(S, hipFuncSetAttribute((const void *)k_obs, hipFuncAttributeMaxDynamicSharedMemorySize, (int)S->lds_stage));
     HIPCHK(S, hipFuncSetAttribute((const void *)k_state, hipFuncAttributeMaxDynamicSharedMemorySize, (int)S->lds_stage));
-    S->persist_ok = (int)S->lds_persist <= maxlds;
-    if (S->persist_ok) {
+    {
+        // dynamic LDS available to k_persist next to its static LDS
+        hipFuncAttributes fa{};
+        HIPCHK(S, hipFuncGetAttributes(&fa, (const void *)k_persist));
+        S->maxlds_persist = maxlds - (int)fa.sharedSizeBytes;
         HIPCHK(S, hipFuncSetAttribute((const void *)k_persist, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)S->lds_persist));
+                                      S->maxlds_persist));
     }
     S->bt_persist = std::min(1024, std::max(64, (n * P + 63) / 64 * 64));
-    if (S->persist_ok) {
-        // default split: a power of two up to 8 workgroups per replica, each owning >= 256
-        // atoms, with every workgroup of the grid resident at once
-        int cus = 0, per_cu = 0;
+    {
+        // persistent split: the fewest workgroups per replica (1, 2, 4 or 8) whose LDS fits, then
+        // more while each keeps >= 256 atoms; with more than one, every workgroup of the grid
+        // must be resident at once (cooperative launch)
+        int cus = 0;
         HIPCHK(S, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        S->max_coresident = cus;
+        auto usable = [&](int G, bool &ok) -> hipError_t {
+            const size_t lds = persist_lds(n, np, make_split(S->work, n, np, G));
+            ok = false;
+            if ((int)lds > S->maxlds_persist) return hipSuccess;
+            if (G == 1) { ok = true; return hipSuccess; }
+            int per_cu = 0;
+            const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_persist,
+                                                                              S->bt_persist, lds);
+            ok = e == hipSuccess && (long)R * G <= (long)per_cu * cus;
+            return e;
+        };
         int G = 1;
-        while (G < 8 && (n + 2 * G - 1) / (2 * G) >= 256) {
-            HIPCHK(S, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_persist, S->bt_persist,
-                                                                  persist_lds(n, np, 2 * G)));
-            if ((long)R * 2 * G > (long)per_cu * cus) break;
-            G *= 2;
+        bool ok = false;
+        for (; G <= 8; G *= 2) {
+            HIPCHK(S, usable(G, ok));
+            if (ok) break;
+        }
+        S->persist_ok = ok ? 1 : 0;
+        if (ok) {
+            while (G < 8 && (n + 2 * G - 1) / (2 * G) >= 256) {
+                bool ok2 = false;
+                HIPCHK(S, usable(2 * G, ok2));
+                if (!ok2) break;
+                G *= 2;
+            }
+        } else {
+            G = 1;
         }
         S->groups = G;
-        S->max_coresident = cus;
+        S->split = make_split(S->work, n, np, G);
+        S->lds_persist = persist_lds(n, np, S->split);
     }
 
     // initial velocities, copies into every replica, forces, Omega and the observable shift
@@ -654,6 +721,8 @@ extern "C" gpr_status gpr_system_create(const gpr_system_desc *D, gpr_system **o
             (D->n_torsions && (!D->torsion_n || !D->torsion_k || !D->torsion_phi0)) ||
             (D->n_restraints && (!D->restraint_ref || !D->restraint_k)))
             return fail(nullptr, GPR_EINVAL, "missing term parameters");
+        for (int t = 0; t < D->n_torsions; ++t)
+            if (D->torsion_n[t] < 0 || D->torsion_n[t] > 12) return fail(nullptr, GPR_EINVAL, "torsion multiplicity outside [0, 12]");
         if (D->cutoff > 0 && (!(D->skin > 0) || !(D->eps_rf >= 1))) return fail(nullptr, GPR_EINVAL, "bad cutoff parameters");
     }
     const gpr_state_desc &st = D->state;
@@ -716,21 +785,28 @@ extern "C" gpr_status gpr_set_launch(gpr_system *S, int32_t block_threads, int32
     if (groups_per_replica != 0 && groups_per_replica != 1 && groups_per_replica != 2 && groups_per_replica != 4 &&
         groups_per_replica != 8)
         return fail(S, GPR_EINVAL, "groups_per_replica must be 1, 2, 4 or 8");
-    if (block_threads != 0) {
-        if (block_threads < 64 || block_threads > 1024 || block_threads % 64)
-            return fail(S, GPR_EINVAL, "block_threads must be a multiple of 64 in [64, 1024]");
-        S->bt_persist = block_threads;
+    if (block_threads != 0 && (block_threads < 64 || block_threads > 1024 || block_threads % 64))
+        return fail(S, GPR_EINVAL, "block_threads must be a multiple of 64 in [64, 1024]");
+    const int bt = block_threads != 0 ? block_threads : S->bt_persist;
+    {
+        const int G = groups_per_replica != 0 ? groups_per_replica : S->groups;
+        const size_t lds = persist_lds(S->n, S->np, make_split(S->work, S->n, S->np, G));
+        if ((int)lds > S->maxlds_persist)
+            return fail(S, GPR_EINVAL, "the per-workgroup LDS of this split exceeds the device limit");
+        if (G > 1) {
+            int dev = 0, cus = 0, per_cu = 0;
+            HIPCHK(S, hipGetDevice(&dev));
+            HIPCHK(S, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+            HIPCHK(S, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_persist, bt, lds));
+            if ((long)S->R * G > (long)per_cu * cus)
+                return fail(S, GPR_EINVAL, "replicas x groups exceed the workgroups the device holds at once");
+        }
     }
-    if (groups_per_replica > 1) {
-        int dev = 0, cus = 0, per_cu = 0;
-        HIPCHK(S, hipGetDevice(&dev));
-        HIPCHK(S, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        HIPCHK(S, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_persist, S->bt_persist,
-                                                              persist_lds(S->n, S->np, groups_per_replica)));
-        if ((long)S->R * groups_per_replica > (long)per_cu * cus)
-            return fail(S, GPR_EINVAL, "replicas x groups exceed the workgroups the device holds at once");
+    S->bt_persist = bt;
+    if (groups_per_replica != 0) {
+        S->groups = groups_per_replica;
+        S->split = make_split(S->work, S->n, S->np, groups_per_replica);
     }
-    if (groups_per_replica != 0) S->groups = groups_per_replica;
     return GPR_OK;
 }
 

@@ -28,8 +28,7 @@ namespace gpr {
 constexpr int P = 4;            // lanes per atom in the pair loop (sub-lists by j mod P)
 constexpr int MAX_OBS = 8;
 constexpr int CHMAX = 4;        // atoms per thread in the integrator mapping
-constexpr int BLK = 32;         // atoms per level-1 bounding sphere in the pair search
-constexpr int BLK2 = 8;         // atoms per level-2 bounding sphere (BLK2 a multiple of P)
+constexpr int BLK = 8;          // consecutive atoms per bounding sphere in the pair search (a multiple of P)
 constexpr double FIX = 4294967296.0;          // 2^32
 constexpr double FIX_INV = 2.3283064365386963e-10;  // 2^-32
 constexpr float FMAX_FIX = 1.0e9f;             // |F| beyond this counts as unstable
@@ -65,7 +64,7 @@ struct StateDesc {
 struct Topo {
     int nb; const int2 *b_ij; const float2 *b_p; const int *b_start; int b_span;            // (r0, k)
     int na; const int4 *a_ijk; const float2 *a_p; const int *a_start; int a_span;           // (theta0, k)
-    int nt; const int4 *t_ijkl; const float4 *t_p; const int *t_start; int t_span;          // (k, phi0, n)
+    int nt; const int4 *t_ijkl; const float4 *t_p; const int *t_start; int t_span;          // (k, cos phi0, sin phi0, n)
     int nr; const int *r_i; const float4 *r_p; const int *r_start;                          // (ref xyz, k)
     int n14; const int2 *p_ij; const float4 *p_p; const int *p_start; int p_span;           // (s, 4e*sc, qq*sc)
 };
@@ -112,6 +111,10 @@ __device__ __forceinline__ const GPR_GLOBAL T *gconst(const T *p) { return (cons
 template <class T>
 __device__ __forceinline__ GPR_GLOBAL T *gmut(T *p) { return (GPR_GLOBAL T *)p; }
 
+// LDS address space, for arrays that a non-inlined function reads (so that it emits LDS, not
+// flat, instructions)
+#define GPR_LDS __attribute__((address_space(3)))
+
 // vector loads/stores through native vector types (HIP's vector classes cannot be copied
 // from an address-space-qualified reference)
 typedef int gv_i2 __attribute__((ext_vector_type(2)));
@@ -125,6 +128,7 @@ __device__ __forceinline__ uint2 gld(const GPR_GLOBAL uint2 *p) { const gv_u2 v 
 __device__ __forceinline__ float2 gld(const GPR_GLOBAL float2 *p) { const gv_f2 v = *(const GPR_GLOBAL gv_f2 *)p; return make_float2(v.x, v.y); }
 __device__ __forceinline__ float4 gld(const GPR_GLOBAL float4 *p) { const gv_f4 v = *(const GPR_GLOBAL gv_f4 *)p; return make_float4(v.x, v.y, v.z, v.w); }
 __device__ __forceinline__ void gst(GPR_GLOBAL uint2 *p, uint2 v) { gv_u2 w; w.x = v.x; w.y = v.y; *(GPR_GLOBAL gv_u2 *)p = w; }
+__device__ __forceinline__ void gst(GPR_GLOBAL unsigned long long *p, unsigned long long v) { *p = v; }
 
 // ------------------------------------------------------------------ Philox4x32-10
 // Salmon, Moraes, Dror, Shaw (SC'11): ten rounds; each multiplies words 0 and 2 by fixed
@@ -187,41 +191,64 @@ __device__ __forceinline__ bool bad_force(float f) { return !(fabsf(f) < FMAX_FI
 // Each returns the energy and writes the force on every atom of the term.
 
 // bond 1/2 k (r - r0)^2
+// arctangent on [0, 1] as a P(a^2), P of degree 8 fitted by iteratively reweighted least
+// squares to atan(a)/a (maximum error 6e-9 in exact arithmetic, 1e-7 evaluated in FP32)
+__device__ __forceinline__ float atan01(float a)
+{
+    const float s = a * a;
+    float p = 0.002454932313412428f;
+    p = fmaf(p, s, -0.014395107515156269f);
+    p = fmaf(p, s, 0.039772968739271164f);
+    p = fmaf(p, s, -0.07234375923871994f);
+    p = fmaf(p, s, 0.10498868674039841f);
+    p = fmaf(p, s, -0.141612708568573f);
+    p = fmaf(p, s, 0.19985927641391754f);
+    p = fmaf(p, s, -0.3333260118961334f);
+    p = fmaf(p, s, 0.9999998807907104f);
+    return a * p;
+}
+// the angle atan2(y, x) in [0, pi] for y >= 0 (octant reduction to [0, 1])
+__device__ __forceinline__ float atan2_upper(float y, float x)
+{
+    const float ax = fabsf(x);
+    const float mx = fmaxf(y, ax), mn = fminf(y, ax);
+    float t = mx > 0.f ? atan01(mn * __builtin_amdgcn_rcpf(mx)) : 0.f;
+    if (y > ax) t = 1.5707963267948966f - t;
+    if (x < 0.f) t = 3.141592653589793f - t;
+    return t;
+}
+
 __device__ __forceinline__ float term_bond(float3 pi, float3 pj, float2 p, float3 &fi)
 {
     const float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-    const float r = sqrtf(dx * dx + dy * dy + dz * dz);
-    const float dr = r - p.x;
-    const float g = p.y * dr / r;   // force on i along (pj - pi)
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float dr = r2 * ri - p.x;
+    const float g = p.y * dr * ri;   // force on i along (pj - pi)
     fi = make_float3(g * dx, g * dy, g * dz);
     return 0.5f * p.y * dr * dr;
 }
-
-// angle 1/2 k (theta - theta0)^2 with theta = atan2(|u x w|, u . w), vertex j
 __device__ __forceinline__ float term_angle(float3 pi, float3 pj, float3 pk, float2 p, float3 &fi, float3 &fk)
 {
     const float ux = pi.x - pj.x, uy = pi.y - pj.y, uz = pi.z - pj.z;
     const float wx = pk.x - pj.x, wy = pk.y - pj.y, wz = pk.z - pj.z;
     const float cx = uy * wz - uz * wy, cy = uz * wx - ux * wz, cz = ux * wy - uy * wx;
-    const float sn = sqrtf(cx * cx + cy * cy + cz * cz);
+    const float sn = __builtin_amdgcn_sqrtf(cx * cx + cy * cy + cz * cz);
     const float cs = ux * wx + uy * wy + uz * wz;
-    const float th = atan2f(sn, cs);
+    const float th = atan2_upper(sn, cs);
     const float dth = th - p.x;
     const float lu2 = ux * ux + uy * uy + uz * uz, lw2 = wx * wx + wy * wy + wz * wz;
     // d theta / d p_i = (cos(theta) u/|u|^2 - w/(|u||w|)) / sin(theta); sin(theta) |u||w| = sn
     const float g = -p.y * dth;
-    const float a = g / sn;                         // g / (|u||w| sin theta)
-    const float cu = cs / lu2, cw = cs / lw2;
+    const float a = g * __builtin_amdgcn_rcpf(sn);          // g / (|u||w| sin theta)
+    const float cu = cs * __builtin_amdgcn_rcpf(lu2), cw = cs * __builtin_amdgcn_rcpf(lw2);
     fi = make_float3(a * (cu * ux - wx), a * (cu * uy - wy), a * (cu * uz - wz));
     fk = make_float3(a * (cw * wx - ux), a * (cw * wy - uy), a * (cw * wz - uz));
     return 0.5f * p.y * dth * dth;
 }
-
-// torsion k (1 + cos(n phi - phi0)); phi from b1 = pj - pi, b2 = pk - pj, b3 = pl - pk:
-// phi = atan2(|b2| b1 . (b2 x b3), (b1 x b2) . (b2 x b3)) (IUPAC, trans = pi).  Gradient
-// (Bekker; Blondel and Karplus 1996): dphi/dp_i = -|b2|/|n1|^2 n1, dphi/dp_l = |b2|/|n2|^2 n2,
-// the middle atoms take the remainder weighted by the projections of b1 and b3 on b2
-// (p12 = b1.b2/|b2|^2, p32 = b3.b2/|b2|^2), so that net force and torque vanish.
+// k (1 + cos(n phi - phi0)) with p = (k, cos phi0, sin phi0, n): cos phi and sin phi come from the
+// two projections that define the dihedral, cos n phi and sin n phi by repeated complex
+// multiplication, so no inverse or direct trigonometric function is evaluated.
 __device__ __forceinline__ float term_torsion(float3 pi, float3 pj, float3 pk, float3 pl, float4 p,
                                               float3 &fi, float3 &fj, float3 &fk, float3 &fl)
 {
@@ -231,35 +258,42 @@ __device__ __forceinline__ float term_torsion(float3 pi, float3 pj, float3 pk, f
     const float n1x = b1y * b2z - b1z * b2y, n1y = b1z * b2x - b1x * b2z, n1z = b1x * b2y - b1y * b2x;
     const float n2x = b2y * b3z - b2z * b3y, n2y = b2z * b3x - b2x * b3z, n2z = b2x * b3y - b2y * b3x;
     const float lb2sq = b2x * b2x + b2y * b2y + b2z * b2z;
-    const float lb2 = sqrtf(lb2sq);
+    const float ilb2 = __builtin_amdgcn_rsqf(lb2sq);
+    const float lb2 = lb2sq * ilb2;
     const float xx = n1x * n2x + n1y * n2y + n1z * n2z;
     const float yy = lb2 * (b1x * n2x + b1y * n2y + b1z * n2z);
-    const float phi = atan2f(yy, xx);
-    const float arg = p.z * phi - p.y;
-    float sa, ca;
-    sincosf(arg, &sa, &ca);
-    const float dUdphi = -p.x * p.z * sa;
+    const float ih = __builtin_amdgcn_rsqf(xx * xx + yy * yy);
+    const float c = xx * ih, sn = yy * ih;                 // cos phi, sin phi
+    float C = 1.0f, Sn = 0.0f;                            // cos n phi, sin n phi
+    const int nm = (int)p.w;
+    for (int m = 0; m < nm; ++m) {
+        const float C2 = C * c - Sn * sn;
+        Sn = C * sn + Sn * c;
+        C = C2;
+    }
+    const float ca = C * p.y + Sn * p.z;                  // cos(n phi - phi0)
+    const float sa = Sn * p.y - C * p.z;                  // sin(n phi - phi0)
+    const float dUdphi = -p.x * p.w * sa;
     const float n1sq = n1x * n1x + n1y * n1y + n1z * n1z;
     const float n2sq = n2x * n2x + n2y * n2y + n2z * n2z;
-    const float ai = dUdphi * lb2 / n1sq;     // F_i = -dU/dphi dphi/dp_i = +dU/dphi |b2|/|n1|^2 n1
-    const float al = -dUdphi * lb2 / n2sq;    // F_l = -dU/dphi |b2|/|n2|^2 n2
+    const float ai = dUdphi * lb2 * __builtin_amdgcn_rcpf(n1sq);    // F_i = +dU/dphi |b2|/|n1|^2 n1
+    const float al = -dUdphi * lb2 * __builtin_amdgcn_rcpf(n2sq);   // F_l = -dU/dphi |b2|/|n2|^2 n2
     fi = make_float3(ai * n1x, ai * n1y, ai * n1z);
     fl = make_float3(al * n2x, al * n2y, al * n2z);
-    const float p12 = (b1x * b2x + b1y * b2y + b1z * b2z) / lb2sq;
-    const float p32 = (b3x * b2x + b3y * b2y + b3z * b2z) / lb2sq;
+    const float ilb2sq = ilb2 * ilb2;
+    const float p12 = (b1x * b2x + b1y * b2y + b1z * b2z) * ilb2sq;
+    const float p32 = (b3x * b2x + b3y * b2y + b3z * b2z) * ilb2sq;
     // F_j = -(1 + p12) F_i + p32 F_l ; F_k = p12 F_i - (1 + p32) F_l
     const float aj = -(1.0f + p12), ak = -(1.0f + p32);
     fj = make_float3(aj * fi.x + p32 * fl.x, aj * fi.y + p32 * fl.y, aj * fi.z + p32 * fl.z);
     fk = make_float3(p12 * fi.x + ak * fl.x, p12 * fi.y + ak * fl.y, p12 * fi.z + ak * fl.z);
     return p.x * (1.0f + ca);
 }
-
-// 1-4 pair: scale (LJ + vacuum Coulomb), parameters pre-multiplied by the scale
 __device__ __forceinline__ float term_pair14(float3 pi, float3 pj, float4 p, float3 &fi)
 {
     const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
     const float r2 = dx * dx + dy * dy + dz * dz;
-    const float ri = 1.0f / sqrtf(r2);
+    const float ri = __builtin_amdgcn_rsqf(r2);
     const float r2i = ri * ri;
     const float s2 = p.x * p.x * r2i;
     const float s6 = s2 * s2 * s2;

@@ -18,13 +18,20 @@ struct Status {
     double rhat[MAX_OBS];
 };
 
+// atom ranges of the workgroups of one replica on the persistent path
+struct Split {
+    int G;          // workgroups per replica (1, 2, 4 or 8)
+    int lmax;       // LDS length of the per-group arrays: the largest range, rounded up to 16
+    int bnd[9];     // group g owns atoms [bnd[g], bnd[g + 1]); every bnd[g] < n is a multiple of 16
+};
+
 __global__ void k_integrate(const Dev *__restrict__ Sp, long long s, int r_off, int energy);
 __global__ void k_bonded(const Dev *__restrict__ Sp, int r_off, int energy);
 __global__ void k_nonbonded(const Dev *__restrict__ Sp, long long s, int r_off, int energy, int apply_b, int force_build);
 __global__ void k_obs(const Dev *__restrict__ Sp, int r_off, int mode, double *out);
 __global__ void k_state(const Dev *__restrict__ Sp, int r_off);
 __global__ void k_persist(const Dev *__restrict__ Sp, long long s0, int nsteps, int t0, int sample, int state_end,
-                          int G, int nrep);
+                          Split sp, int nrep);
 __global__ void k_check(const Dev *__restrict__ Sp, int mode, long long s, int omega, int nrep, long long nsamp, int check_index,
                         Status *st, int *donor, int *surv, long long *fec);
 __global__ void k_clone(const Dev *__restrict__ Sp, const int *donor, int acc_mode);

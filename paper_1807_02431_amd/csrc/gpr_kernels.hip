@@ -44,19 +44,46 @@ struct PosGlob {
 __device__ __forceinline__ float3 neg3(float3 f) { return make_float3(-f.x, -f.y, -f.z); }
 
 // ------------------------------------------------------------------ bonded terms of an atom range
-// Adds, for every term touching atoms [a0, a1), the fixed-point forces on the atoms of the
-// range to fa[3][len] (LDS, index a - a0); the energy of a term is counted by the range
-// holding its smallest atom.
-template <class Pos>
-__device__ void bonded_range(const Dev &S, const Pos &pos, int a0, int a1, long long *fa, int len,
-                             long long *e_acc, int tid, int nthr)
+// Terms touching atoms [a0, a1), by kind (bond, angle, torsion, restraint, 1-4): topology
+// entries [lo[k], lo[k] + cnt[k]) of kind k occupy the slots [off[k], off[k] + cnt[k]) of one
+// flat index space in which every kind starts at a multiple of 64 (so a wave sees one kind).
+struct BondedPlan {
+    int lo[5], cnt[5], off[6];
+};
+
+__device__ __forceinline__ BondedPlan bonded_plan(const Dev &S, int a0, int a1)
 {
     const Topo &T = S.tp;
-    const GPR_GLOBAL int2 *b_ij = gconst(T.b_ij); const GPR_GLOBAL float2 *b_p = gconst(T.b_p);
-    const GPR_GLOBAL int4 *a_ijk = gconst(T.a_ijk); const GPR_GLOBAL float2 *a_p = gconst(T.a_p);
-    const GPR_GLOBAL int4 *t_ijkl = gconst(T.t_ijkl); const GPR_GLOBAL float4 *t_p = gconst(T.t_p);
-    const GPR_GLOBAL int *r_i = gconst(T.r_i); const GPR_GLOBAL float4 *r_p = gconst(T.r_p);
-    const GPR_GLOBAL int2 *p_ij = gconst(T.p_ij); const GPR_GLOBAL float4 *p_p = gconst(T.p_p);
+    BondedPlan bp;
+    auto range = [&](int k, int nterm, const int *start, int span) {
+        int lo = 0, hi = 0;
+        if (nterm) {
+            lo = gconst(start)[max(0, a0 - span)];
+            hi = gconst(start)[a1];
+        }
+        bp.lo[k] = lo;
+        bp.cnt[k] = hi - lo;
+    };
+    range(0, T.nb, T.b_start, T.b_span);
+    range(1, T.na, T.a_start, T.a_span);
+    range(2, T.nt, T.t_start, T.t_span);
+    range(3, T.nr, T.r_start, 0);
+    range(4, T.n14, T.p_start, T.p_span);
+    bp.off[0] = 0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) bp.off[k + 1] = bp.off[k] + (bp.cnt[k] + 63) / 64 * 64;
+    return bp;
+}
+
+// Adds, for every term of the plan, the fixed-point forces on the atoms of [a0, a1) to
+// fa[3][len] (LDS, index a - a0); the energy of a term is counted by the range holding its
+// smallest atom.  Each thread takes up to four slots at a time and issues all their topology
+// loads before computing any of them.  nthr must be a multiple of 64.
+template <class Pos>
+__device__ void bonded_range(const Dev &S, const BondedPlan &bp, const Pos &pos, int a0, int a1, long long *fa,
+                             int len, long long *e_acc, int tid, int nthr)
+{
+    const Topo &T = S.tp;
     auto add = [&](int a, float3 f) {
         if (a >= a0 && a < a1) {
             lds_add(&fa[a - a0], fix_f(f.x));
@@ -64,67 +91,96 @@ __device__ void bonded_range(const Dev &S, const Pos &pos, int a0, int a1, long 
             lds_add(&fa[2 * len + a - a0], fix_f(f.z));
         }
     };
+    constexpr int U = 4;
     long long e = 0;
-    if (T.nb) {
-        const int lo = gconst(T.b_start)[max(0, a0 - T.b_span)], hi = gconst(T.b_start)[a1];
-        for (int t = lo + tid; t < hi; t += nthr) {
-            const int2 ij = gld(b_ij + t);
-            float3 fi;
-            const float u = term_bond(pos(ij.x), pos(ij.y), gld(b_p + t), fi);
-            add(ij.x, fi);
-            add(ij.y, neg3(fi));
-            const int mn = min(ij.x, ij.y);
-            if (e_acc && mn >= a0) e += fix_f(u);
+    const int total = bp.off[5];
+    for (int base = 0; base < total; base += U * nthr) {
+        int kind[U];
+        int4 idx[U];
+        float4 prm[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int slot = base + u * nthr + tid;
+            // kind and topology index of the slot (static indices into the plan: no scratch)
+            int k = -1, t = 0;
+            if (slot < total) {
+                int local, cnt, lo;
+                if (slot < bp.off[1]) { k = 0; local = slot; cnt = bp.cnt[0]; lo = bp.lo[0]; }
+                else if (slot < bp.off[2]) { k = 1; local = slot - bp.off[1]; cnt = bp.cnt[1]; lo = bp.lo[1]; }
+                else if (slot < bp.off[3]) { k = 2; local = slot - bp.off[2]; cnt = bp.cnt[2]; lo = bp.lo[2]; }
+                else if (slot < bp.off[4]) { k = 3; local = slot - bp.off[3]; cnt = bp.cnt[3]; lo = bp.lo[3]; }
+                else { k = 4; local = slot - bp.off[4]; cnt = bp.cnt[4]; lo = bp.lo[4]; }
+                if (local >= cnt) k = -1;
+                t = lo + local;
+            }
+            kind[u] = k;
+            idx[u] = make_int4(0, 0, 0, 0);
+            prm[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (k < 0) continue;
+            if (k == 0) {
+                const int2 ij = gld(gconst(T.b_ij) + t);
+                const float2 p = gld(gconst(T.b_p) + t);
+                idx[u] = make_int4(ij.x, ij.y, 0, 0);
+                prm[u] = make_float4(p.x, p.y, 0.f, 0.f);
+            } else if (k == 1) {
+                idx[u] = gld(gconst(T.a_ijk) + t);
+                const float2 p = gld(gconst(T.a_p) + t);
+                prm[u] = make_float4(p.x, p.y, 0.f, 0.f);
+            } else if (k == 2) {
+                idx[u] = gld(gconst(T.t_ijkl) + t);
+                prm[u] = gld(gconst(T.t_p) + t);
+            } else if (k == 3) {
+                idx[u] = make_int4(gconst(T.r_i)[t], 0, 0, 0);
+                prm[u] = gld(gconst(T.r_p) + t);
+            } else {
+                const int2 ij = gld(gconst(T.p_ij) + t);
+                idx[u] = make_int4(ij.x, ij.y, 0, 0);
+                prm[u] = gld(gconst(T.p_p) + t);
+            }
         }
-    }
-    if (T.na) {
-        const int lo = gconst(T.a_start)[max(0, a0 - T.a_span)], hi = gconst(T.a_start)[a1];
-        for (int t = lo + tid; t < hi; t += nthr) {
-            const int4 q = gld(a_ijk + t);
-            float3 fi, fk;
-            const float u = term_angle(pos(q.x), pos(q.y), pos(q.z), gld(a_p + t), fi, fk);
-            add(q.x, fi);
-            add(q.z, fk);
-            add(q.y, make_float3(-fi.x - fk.x, -fi.y - fk.y, -fi.z - fk.z));
-            const int mn = min(q.x, min(q.y, q.z));
-            if (e_acc && mn >= a0) e += fix_f(u);
-        }
-    }
-    if (T.nt) {
-        const int lo = gconst(T.t_start)[max(0, a0 - T.t_span)], hi = gconst(T.t_start)[a1];
-        for (int t = lo + tid; t < hi; t += nthr) {
-            const int4 q = gld(t_ijkl + t);
-            float3 fi, fj, fk, fl;
-            const float u = term_torsion(pos(q.x), pos(q.y), pos(q.z), pos(q.w), gld(t_p + t), fi, fj, fk, fl);
-            add(q.x, fi);
-            add(q.y, fj);
-            add(q.z, fk);
-            add(q.w, fl);
-            const int mn = min(min(q.x, q.y), min(q.z, q.w));
-            if (e_acc && mn >= a0) e += fix_f(u);
-        }
-    }
-    if (T.nr) {
-        const int lo = gconst(T.r_start)[a0], hi = gconst(T.r_start)[a1];
-        for (int t = lo + tid; t < hi; t += nthr) {
-            const int a = r_i[t];
-            const float4 p = gld(r_p + t);
-            const float3 x = pos(a);
-            const float dx = x.x - p.x, dy = x.y - p.y, dz = x.z - p.z;
-            add(a, make_float3(-p.w * dx, -p.w * dy, -p.w * dz));
-            if (e_acc) e += fix_f(0.5f * p.w * (dx * dx + dy * dy + dz * dz));
-        }
-    }
-    if (T.n14) {
-        const int lo = gconst(T.p_start)[max(0, a0 - T.p_span)], hi = gconst(T.p_start)[a1];
-        for (int t = lo + tid; t < hi; t += nthr) {
-            const int2 ij = gld(p_ij + t);
-            float3 fi;
-            const float u = term_pair14(pos(ij.x), pos(ij.y), gld(p_p + t), fi);
-            add(ij.x, fi);
-            add(ij.y, neg3(fi));
-            const int mn = min(ij.x, ij.y);
-            if (e_acc && mn >= a0) e += fix_f(u);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = kind[u];
+            if (k < 0) continue;
+            const int4 q = idx[u];
+            const float4 p = prm[u];
+            float u_e;
+            int mn;
+            if (k == 0) {
+                float3 fi;
+                u_e = term_bond(pos(q.x), pos(q.y), make_float2(p.x, p.y), fi);
+                add(q.x, fi);
+                add(q.y, neg3(fi));
+                mn = min(q.x, q.y);
+            } else if (k == 1) {
+                float3 fi, fk;
+                u_e = term_angle(pos(q.x), pos(q.y), pos(q.z), make_float2(p.x, p.y), fi, fk);
+                add(q.x, fi);
+                add(q.z, fk);
+                add(q.y, make_float3(-fi.x - fk.x, -fi.y - fk.y, -fi.z - fk.z));
+                mn = min(q.x, min(q.y, q.z));
+            } else if (k == 2) {
+                float3 fi, fj, fk, fl;
+                u_e = term_torsion(pos(q.x), pos(q.y), pos(q.z), pos(q.w), p, fi, fj, fk, fl);
+                add(q.x, fi);
+                add(q.y, fj);
+                add(q.z, fk);
+                add(q.w, fl);
+                mn = min(min(q.x, q.y), min(q.z, q.w));
+            } else if (k == 3) {
+                const float3 x = pos(q.x);
+                const float dx = x.x - p.x, dy = x.y - p.y, dz = x.z - p.z;
+                add(q.x, make_float3(-p.w * dx, -p.w * dy, -p.w * dz));
+                u_e = 0.5f * p.w * (dx * dx + dy * dy + dz * dz);
+                mn = q.x;
+            } else {
+                float3 fi;
+                u_e = term_pair14(pos(q.x), pos(q.y), p, fi);
+                add(q.x, fi);
+                add(q.y, neg3(fi));
+                mn = min(q.x, q.y);
+            }
+            if (e_acc && mn >= a0) e += fix_f(u_e);
         }
     }
     if (e_acc && e != 0) lds_add(e_acc, e);
@@ -140,16 +196,13 @@ __device__ __forceinline__ float toy_force(float x, float y, float &fx, float &f
 }
 
 // ------------------------------------------------------------------ pair search
-// Bounding spheres of blocks of consecutive atoms (chain-local, so compact): BLK atoms
-// (level 1) and BLK2 atoms (level 2).  Each radius is padded slightly so that rounding
-// cannot drop a pair.
-__device__ void block_spheres(const Dev &S, const float4 *xs, float4 *sph, float4 *sph2, int tid, int nthr)
+// Bounding spheres of blocks of BLK consecutive atoms (chain-local, so compact).  Each radius
+// is padded slightly so that rounding cannot drop a pair.
+__device__ void block_spheres(const Dev &S, const float4 *xs, float4 *sph, int tid, int nthr)
 {
-    const int nblk = (S.n + BLK - 1) / BLK, nblk2 = (S.n + BLK2 - 1) / BLK2;
-    for (int t = tid; t < nblk + nblk2; t += nthr) {
-        const bool l1 = t < nblk;
-        const int size = l1 ? BLK : BLK2;
-        const int a0 = (l1 ? t : t - nblk) * size, a1 = min(S.n, a0 + size);
+    const int nblk = (S.n + BLK - 1) / BLK;
+    for (int t = tid; t < nblk; t += nthr) {
+        const int a0 = t * BLK, a1 = min(S.n, a0 + BLK);
         float cx = 0.f, cy = 0.f, cz = 0.f;
         for (int a = a0; a < a1; ++a) { cx += xs[a].x; cy += xs[a].y; cz += xs[a].z; }
         const float inv = 1.0f / (float)(a1 - a0);
@@ -159,60 +212,102 @@ __device__ void block_spheres(const Dev &S, const float4 *xs, float4 *sph, float
             const float dx = xs[a].x - cx, dy = xs[a].y - cy, dz = xs[a].z - cz;
             r2 = fmaxf(r2, dx * dx + dy * dy + dz * dz);
         }
-        const float4 c = make_float4(cx, cy, cz, sqrtf(r2) * 1.0001f + 1e-6f);
-        if (l1) sph[t] = c;
-        else sph2[t - nblk] = c;
+        sph[t] = make_float4(cx, cy, cz, sqrtf(r2) * 1.0001f + 1e-6f);
     }
 }
 
-__device__ __forceinline__ bool sphere_near(const float4 pi, const float4 c, float rl)
+// min / max over the 16 atoms of a wave (the four lanes of an atom hold the same value)
+__device__ __forceinline__ float wave16_min(float v)
 {
-    const float dx = pi.x - c.x, dy = pi.y - c.y, dz = pi.z - c.z;
-    const float lim = rl + c.w;
-    return dx * dx + dy * dy + dz * dz < lim * lim;
+#pragma unroll
+    for (int o = 4; o < 64; o <<= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ float wave16_max(float v)
+{
+#pragma unroll
+    for (int o = 4; o < 64; o <<= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
 }
 
+// Pair lists of the 16 atoms of one wave; lane = 4 (i - i0) + q for the wave's first atom
+// i0.  All 64 lanes call it together: the culling is wave-wide (each lane tests a block
+// sphere against the bounding sphere of the wave's atoms, and the wave visits the blocks that
+// any lane found near); lanes with valid == false take part but own no list.
 // Sub-list (i, q): partners j = q (mod P), j != i, not excluded, |x_i - x_j| < r_list, in
-// ascending order; entry k is the 16-bit word k % 4 of group k / 4; the last group is
-// padded with the dummy atom.  Candidates come from the level-2 blocks inside level-1 blocks
-// whose spheres reach within r_list.  allpairs: no distance tests (vacuum, no cutoff).
-__device__ __noinline__ void build_lane(const Dev &S, int r, int i, int q, const float4 *xs, const float4 *sph,
-                                        const float4 *sph2, bool allpairs)
+// ascending order; entry k is the 16-bit word k % 4 of group k / 4; the last group is padded
+// with the dummy atom n.  allpairs: no distance tests (vacuum, no cutoff).
+__device__ __noinline__ void build_wave(const Dev &S, int r, int i, int q, bool valid, const GPR_LDS gv_f4 *xs,
+                                        const GPR_LDS gv_f4 *sph, bool allpairs)
 {
+    const int n = S.n;
     const size_t stride = (size_t)S.np * P;
-    GPR_GLOBAL unsigned short *L = (GPR_GLOBAL unsigned short *)(gmut(S.nbl) + (size_t)r * S.Kg * stride +
-                                                                   (size_t)i * P + q);
-    const float4 pi = xs[i];
-    const unsigned long long ex = gconst(S.excl)[i];
-    const int nblk = (S.n + BLK - 1) / BLK, nblk2 = (S.n + BLK2 - 1) / BLK2;
+    const gv_f4 pi = xs[valid ? i : n];
+    // bounding sphere of the wave's valid atoms
+    const float big = 3.0e38f;
+    const float mnx = wave16_min(valid ? pi.x : big), mxx = wave16_max(valid ? pi.x : -big);
+    if (!(mnx <= mxx)) return;                                  // no valid lane in this wave
+    const float mny = wave16_min(valid ? pi.y : big), mxy = wave16_max(valid ? pi.y : -big);
+    const float mnz = wave16_min(valid ? pi.z : big), mxz = wave16_max(valid ? pi.z : -big);
+    const float cx = 0.5f * (mnx + mxx), cy = 0.5f * (mny + mxy), cz = 0.5f * (mnz + mxz);
+    float d2 = 0.f;
+    if (valid) {
+        const float dx = pi.x - cx, dy = pi.y - cy, dz = pi.z - cz;
+        d2 = dx * dx + dy * dy + dz * dz;
+    }
+    const float rw = S.rl + sqrtf(wave16_max(d2)) * 1.0001f + 1e-6f;
+    const float rl2 = S.rl2;
+    const unsigned long long ex = valid ? gconst(S.excl)[i] : 0ull;
     const int cap = 4 * S.Kg;
-    const float rl = S.rl, rl2 = S.rl2;
+    GPR_GLOBAL unsigned long long *L =
+        (GPR_GLOBAL unsigned long long *)gmut(S.nbl) + (size_t)r * S.Kg * stride + (size_t)(valid ? i : 0) * P + q;
+    const int lane = threadIdx.x & 63;
+    const int nblk = (n + BLK - 1) / BLK;
+    unsigned long long word = 0ull;
     int cnt = 0;
-    for (int b = 0; b < nblk; ++b) {
-        if (!allpairs && !sphere_near(pi, sph[b], rl)) continue;
-        for (int b2 = b * (BLK / BLK2); b2 < min(nblk2, (b + 1) * (BLK / BLK2)); ++b2) {
-            if (!allpairs && !sphere_near(pi, sph2[b2], rl)) continue;
+    for (int cb = 0; cb < nblk; cb += 64) {
+        const int b = cb + lane;
+        bool near = b < nblk;
+        if (near && !allpairs) {
+            const gv_f4 c = sph[b];
+            const float dx = c.x - cx, dy = c.y - cy, dz = c.z - cz;
+            const float lim = rw + c.w;
+            near = dx * dx + dy * dy + dz * dz < lim * lim;
+        }
+        unsigned long long m = __ballot(near);
+        while (m) {
+            const int bb = cb + __builtin_ctzll(m);
+            m &= m - 1ull;
 #pragma unroll
-            for (int t = 0; t < BLK2 / P; ++t) {
-                const int j = b2 * BLK2 + q + t * P;
+            for (int t = 0; t < BLK / P; ++t) {
+                const int j = bb * BLK + q + t * P;
                 const int off = j - i;
                 const bool excl = off >= -32 && off < 32 && ((ex >> (off + 32)) & 1ull);
-                bool take = j < S.n && j != i && !excl;
-                if (!allpairs && take) {
-                    const float4 pj = xs[j];
+                bool take = valid && j < n && j != i && !excl;
+                if (!allpairs) {
+                    const gv_f4 pj = xs[min(j, n)];
                     const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-                    take = fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < rl2;
+                    take = take && fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < rl2;
                 }
                 if (take) {
-                    if (cnt < cap) L[((size_t)(cnt >> 2) * stride) * 4 + (cnt & 3)] = (unsigned short)j;
+                    if (cnt < cap) {
+                        word |= (unsigned long long)j << (16 * (cnt & 3));
+                        if ((cnt & 3) == 3) {
+                            gst(L + (size_t)(cnt >> 2) * stride, word);
+                            word = 0ull;
+                        }
+                    }
                     ++cnt;
                 }
             }
         }
     }
+    if (!valid) return;
     const int ng = (cnt + 3) >> 2;
-    for (int k = cnt; k < 4 * ng; ++k)
-        if (k < cap) L[((size_t)(k >> 2) * stride) * 4 + (k & 3)] = (unsigned short)S.n;
+    if ((cnt & 3) != 0 && cnt < cap) {
+        for (int k = cnt & 3; k < 4; ++k) word |= (unsigned long long)n << (16 * k);
+        gst(L + (size_t)(cnt >> 2) * stride, word);
+    }
     gmut(S.nbc)[(size_t)r * stride + (size_t)i * P + q] = (unsigned short)min(ng, S.Kg);
     if (cnt > cap) atomicOr(&S.err[ERR_LIST], 1);
 }
@@ -520,7 +615,8 @@ __global__ void __launch_bounds__(256) k_bonded(const Dev *__restrict__ Sp, int 
             if (energy) e_acc = fix_f(u);
         }
     } else {
-        bonded_range(S, PosGlob{gconst(S.x) + b, S.np}, a0, a1, fa, len, energy ? &e_acc : nullptr, tid, len);
+        bonded_range(S, bonded_plan(S, a0, a1), PosGlob{gconst(S.x) + b, S.np}, a0, a1, fa, len,
+                     energy ? &e_acc : nullptr, tid, len);
     }
     __syncthreads();
     const int a = a0 + tid;
@@ -543,7 +639,6 @@ __global__ void __launch_bounds__(1024) k_nonbonded(const Dev *__restrict__ Sp, 
     float4 *xs = (float4 *)lds_raw;
     float2 *pp = (float2 *)(xs + S.np);
     float4 *sph = (float4 *)(pp + S.np);
-    float4 *sph2 = sph + (S.n + BLK - 1) / BLK;
     __shared__ long long e_acc;
     const int r = r_off + blockIdx.y;
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -559,13 +654,11 @@ __global__ void __launch_bounds__(1024) k_nonbonded(const Dev *__restrict__ Sp, 
     const int q = tid % P;
     const size_t b = (size_t)r * 3 * S.np;
     if (rebuild) {
-        block_spheres(S, xs, sph, sph2, tid, nthr);
+        block_spheres(S, xs, sph, tid, nthr);
         __syncthreads();
-        if (i < S.n) {
-            build_lane(S, r, i, q, xs, sph, sph2, !S.cutoff_on);
-            if (q == 0) {
-                S.xb[b + i] = xs[i].x; S.xb[b + S.np + i] = xs[i].y; S.xb[b + 2 * S.np + i] = xs[i].z;
-            }
+        build_wave(S, r, i, q, i < S.n, (const GPR_LDS gv_f4 *)xs, (const GPR_LDS gv_f4 *)sph, !S.cutoff_on);
+        if (i < S.n && q == 0) {
+            S.xb[b + i] = xs[i].x; S.xb[b + S.np + i] = xs[i].y; S.xb[b + 2 * S.np + i] = xs[i].z;
         }
         __syncthreads();
     }
@@ -669,9 +762,20 @@ __device__ __forceinline__ bool group_barrier(int *ctr, int target, int *err, in
 
 __device__ __forceinline__ void st_coh(float *p, float v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 __device__ __forceinline__ float ld_coh(const float *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+// (x, y) of one atom as one 64-bit word, for the position exchange
+__device__ __forceinline__ void st_coh2(unsigned long long *p, float x, float y)
+{
+    const unsigned long long w = (unsigned long long)__float_as_uint(x) | ((unsigned long long)__float_as_uint(y) << 32);
+    __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float2 ld_coh2(const unsigned long long *p)
+{
+    const unsigned long long w = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_float2(__uint_as_float((unsigned)w), __uint_as_float((unsigned)(w >> 32)));
+}
 
 // G workgroups per replica advance nsteps BAOAB steps.  Group g of replica r owns the atoms
-// [a0, a1) (chunk = ceil(n / G) rounded to 16); its LDS holds the positions (float4 with the
+// [a0, a1) = [sp.bnd[g], sp.bnd[g + 1]) (ranges chosen on the host to even out the work); its LDS holds the positions (float4 with the
 // scaled charge) and LJ parameters of every atom of the replica, and the velocities and
 // fixed-point force accumulators of its own atoms (the accumulators carry the forces from one
 // step to the next), block spheres and reduction scratch.  Per step: B A O A of own atoms ->
@@ -682,21 +786,22 @@ __device__ __forceinline__ float ld_coh(const float *p) { return __hip_atomic_lo
 // Workgroups map to replicas so that a replica's groups share an XCD (blockIdx mod 8) when the
 // replica count allows; results do not depend on G or the block size.
 __global__ void __launch_bounds__(1024) k_persist(const Dev *__restrict__ Sp, long long s0, int nsteps, int t0,
-                                                  int sample, int state_end, int G, int nrep)
+                                                  int sample, int state_end, Split sp, int nrep)
 {
     const Dev &S = *Sp;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int np = S.np, n = S.n;
-    const int chunk = G == 1 ? np : ((n + G - 1) / G + 15) / 16 * 16;
-    const int lmax = chunk;
+    const int G = sp.G, lmax = sp.lmax;
     long long *fa = (long long *)lds_raw;                 // [3][lmax]
     long long *red = fa + 3 * lmax;                        // [MAX_OBS * 8 + 8]
     double *vals = (double *)(red + MAX_OBS * 8 + 8);      // [MAX_OBS]
     float4 *xs = (float4 *)(vals + MAX_OBS);               // [np]
     float2 *pp = (float2 *)(xs + np);                      // [np]
     float *vs = (float *)(pp + np);                        // [3][lmax]
-    float4 *sph = (float4 *)(vs + 3 * lmax);               // [nblk]
-    float4 *sph2 = sph + (n + BLK - 1) / BLK;              // [nblk2]
+    float *iml = vs + 3 * lmax;                            // [lmax] 1/m of own atoms
+    float *sdl = iml + lmax;                               // [lmax] noise amplitude of own atoms
+    float *xbl = sdl + lmax;                               // [3][lmax] own positions at the last list build
+    float4 *sph = (float4 *)(xbl + 3 * lmax);              // [nblk]
     __shared__ int sbuf, bbuf, hbuf;
 
     int r, g;
@@ -710,7 +815,7 @@ __global__ void __launch_bounds__(1024) k_persist(const Dev *__restrict__ Sp, lo
         r = blockIdx.x / G; g = blockIdx.x % G;
     }
     if (r >= nrep) return;
-    const int a0 = min(n, g * chunk), a1 = min(n, a0 + chunk);
+    const int a0 = sp.bnd[g], a1 = sp.bnd[g + 1];
     const int tid = threadIdx.x, BT = blockDim.x;
     const size_t b = (size_t)r * 3 * np;
     GPR_GLOBAL float *xg = gmut(S.x) + b, *xbg = gmut(S.xb) + b;
@@ -719,7 +824,8 @@ __global__ void __launch_bounds__(1024) k_persist(const Dev *__restrict__ Sp, lo
     const GPR_GLOBAL float4 *prm = gconst(S.prm);
     const GPR_GLOBAL float *sdv = gconst(S.sd);
     int *sync = S.sync + (size_t)r * 64;
-    float *xch = S.xchg + b;
+    unsigned long long *xch_xy = (unsigned long long *)(S.xchg + b);   // [np] (x, y)
+    float *xch_z = S.xchg + b + 2 * np;                                   // [np] z
     int gen = 0;
 
     stage_replica(S, r, xs, pp, tid, BT);
@@ -727,10 +833,17 @@ __global__ void __launch_bounds__(1024) k_persist(const Dev *__restrict__ Sp, lo
         const int d = k / lmax, a = a0 + k % lmax;
         vs[k] = a < a1 ? gconst(vg)[d * np + a] : 0.f;
         fa[k] = a < a1 ? Fg[d * np + a] : 0;
+        xbl[k] = a < a1 ? xbg[d * np + a] : 0.f;
+    }
+    for (int l = tid; l < lmax; l += BT) {
+        const int a = a0 + l;
+        iml[l] = a < a1 ? gld(prm + a).w : 0.f;
+        sdl[l] = a < a1 ? sdv[a] : 0.f;
     }
     bool need = S.need_build[r] != 0;
     __syncthreads();
     const bool toy = S.kind == KIND_TOY;
+    const BondedPlan bplan = bonded_plan(S, a0, a1);
     long long *eacc = red + MAX_OBS * 8;
     bool alive = true;
 
@@ -745,13 +858,13 @@ __global__ void __launch_bounds__(1024) k_persist(const Dev *__restrict__ Sp, lo
             float3 x = make_float3(xs[a].x, xs[a].y, xs[a].z);
             float3 v = make_float3(vs[l], vs[lmax + l], vs[2 * lmax + l]);
             const float3 F = make_float3(unfix_f(fa[l]), unfix_f(fa[lmax + l]), unfix_f(fa[2 * lmax + l]));
-            integrate_baoa(S, a, r, s, x, v, F, gld(prm + a).w, sdv[a]);
+            integrate_baoa(S, a, r, s, x, v, F, iml[l], sdl[l]);
             xs[a].x = x.x; xs[a].y = x.y; xs[a].z = x.z;
             vs[l] = v.x; vs[lmax + l] = v.y; vs[2 * lmax + l] = v.z;
-            if (G > 1) { st_coh(xch + a, x.x); st_coh(xch + np + a, x.y); st_coh(xch + 2 * np + a, x.z); }
+            if (G > 1) { st_coh2(xch_xy + a, x.x, x.y); st_coh(xch_z + a, x.z); }
             bad |= !(finite3(x) && finite3(v));
             if (S.cutoff_on) {
-                const float dx = x.x - xbg[a], dy = x.y - xbg[np + a], dz = x.z - xbg[2 * np + a];
+                const float dx = x.x - xbl[l], dy = x.y - xbl[lmax + l], dz = x.z - xbl[2 * lmax + l];
                 hit |= !(dx * dx + dy * dy + dz * dz <= S.half_skin2);
             }
         }
@@ -766,7 +879,8 @@ __global__ void __launch_bounds__(1024) k_persist(const Dev *__restrict__ Sp, lo
             if (tid == 0) hbuf = __hip_atomic_load(sync + 16 + 16 * (int)(s % 3), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             for (int a = tid; a < n; a += BT) {
                 if (a >= a0 && a < a1) continue;
-                xs[a].x = ld_coh(xch + a); xs[a].y = ld_coh(xch + np + a); xs[a].z = ld_coh(xch + 2 * np + a);
+                const float2 xy = ld_coh2(xch_xy + a);
+                xs[a].x = xy.x; xs[a].y = xy.y; xs[a].z = ld_coh(xch_z + a);
             }
             __syncthreads();
             any_hit = hbuf;
@@ -774,12 +888,17 @@ __global__ void __launch_bounds__(1024) k_persist(const Dev *__restrict__ Sp, lo
             any_hit = __syncthreads_or(hit);
         }
         if (S.cutoff_on && (need || any_hit || ((s + 1) % S.period == 0))) {
-            block_spheres(S, xs, sph, sph2, tid, BT);
+            block_spheres(S, xs, sph, tid, BT);
             __syncthreads();
-            for (int L = a0 * P + tid; L < a1 * P; L += BT) {
-                const int i = L / P, q = L % P;
-                build_lane(S, r, i, q, xs, sph, sph2, false);
-                if (q == 0) { xbg[i] = xs[i].x; xbg[np + i] = xs[i].y; xbg[2 * np + i] = xs[i].z; }
+            for (int L0 = a0 * P; L0 < a1 * P; L0 += BT) {
+                if (L0 + (tid & ~63) >= a1 * P) continue;          // whole wave past the group's atoms
+                const int L = L0 + tid, i = L / P, q = L % P;
+                const bool valid = L < a1 * P;
+                build_wave(S, r, i, q, valid, (const GPR_LDS gv_f4 *)xs, (const GPR_LDS gv_f4 *)sph, false);
+                if (valid && q == 0) {
+                    const int l = i - a0;
+                    xbl[l] = xs[i].x; xbl[lmax + l] = xs[i].y; xbl[2 * lmax + l] = xs[i].z;
+                }
             }
             need = false;
         }
@@ -795,7 +914,7 @@ __global__ void __launch_bounds__(1024) k_persist(const Dev *__restrict__ Sp, lo
                 if (energy) *eacc = fix_f(u);
             }
         } else {
-            bonded_range(S, PosLDS{xs}, a0, a1, fa, lmax, energy ? eacc : nullptr, tid, BT);
+            bonded_range(S, bplan, PosLDS{xs}, a0, a1, fa, lmax, energy ? eacc : nullptr, tid, BT);
             for (int L0 = a0 * P; L0 < a1 * P; L0 += BT) {
                 const int L = L0 + tid;
                 const int i = L / P, q = L % P;
@@ -823,7 +942,7 @@ __global__ void __launch_bounds__(1024) k_persist(const Dev *__restrict__ Sp, lo
         __syncthreads();
         for (int a = a0 + tid; a < a1; a += BT) {
             const int l = a - a0;
-            const float im = gld(prm + a).w, h = S.h;
+            const float im = iml[l], h = S.h;
             const float Fx = unfix_f(fa[l]), Fy = unfix_f(fa[lmax + l]), Fz = unfix_f(fa[2 * lmax + l]);
             vs[l] = kick(vs[l], Fx, h, im);
             vs[lmax + l] = kick(vs[lmax + l], Fy, h, im);
@@ -868,6 +987,7 @@ __global__ void __launch_bounds__(1024) k_persist(const Dev *__restrict__ Sp, lo
         for (int d = 0; d < 3; ++d) {
             gmut(vg)[d * np + a] = vs[d * lmax + l];
             Fg[d * np + a] = fa[d * lmax + l];
+            xbg[d * np + a] = xbl[d * lmax + l];
         }
     }
     if (g == 0 && tid == 0 && nsteps > 0) S.need_build[r] = 0;
