@@ -127,7 +127,10 @@ typedef struct gpr_system_desc {
     double  cutoff;              /* 0 = all pairs with vacuum Coulomb; > 0 = cutoff with reaction field */
     double  eps_rf;              /* reaction-field dielectric (cutoff > 0) */
     double  skin;                /* pair-list skin (nm), cutoff > 0 */
-    int32_t nlist_period;        /* pair-list rebuild period in steps (a displacement guard also rebuilds) */
+    int32_t nlist_period;        /* pair lists are at most this many steps old (persistent path: per replica;
+                                    plain path: on the steps s with s+1 a multiple of it, for all replicas);
+                                    rebuilt earlier when an atom has moved more than skin/2 since the last
+                                    build.  Results do not depend on when lists are rebuilt. */
 
     int32_t n_bonds;     const int32_t *bond_atoms;     const double *bond_r0;      const double *bond_k;
     int32_t n_angles;    const int32_t *angle_atoms;    const double *angle_theta0; const double *angle_k;

@@ -214,7 +214,7 @@ static size_t persist_lds(int n, int np, const Split &sp)
     const int lmax = sp.lmax;
     const int nblk = (n + BLK - 1) / BLK;
     return (size_t)3 * lmax * 8 + (MAX_OBS * 8 + 8) * 8 + MAX_OBS * 8 + (size_t)np * 16 + (size_t)np * 8 +
-           (size_t)8 * lmax * 4 + (size_t)nblk * 16;
+           (size_t)8 * lmax * 4 + (size_t)nblk * 16 + (size_t)16 * WBLK * 4;
 }
 
 // ------------------------------------------------------------------ launches
@@ -225,6 +225,7 @@ static gpr_status launch_forces(gpr_system *S, int r_off, int nrep, long long s,
                                 bool timed = false)
 {
     const int BTB = 256, BTN = 1024;
+    if (force_build) s = S->s - 1;             // a forced build counts as built in the previous step
     if (energy && force_build) {
         HIPCHK(S, hipMemsetAsync(S->d.E + r_off, 0, sizeof(long long) * nrep, S->stream));
     }
@@ -530,7 +531,8 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
     }
     // capacity from the initial structure: the largest sub-list within r_list, doubled
     // per-atom work estimate for the persistent split: partners within r_list plus a constant
-    // for the bonded terms and the integrator (about 32 pair evaluations' worth per atom)
+    // for the bonded terms, the integrator and the list build (about 72 pair evaluations' worth
+    // per atom, fitted to measured per-group phase times)
     int maxsub = 0;
     S->work.assign(n, 1.0);
     if (D->kind == GPR_KIND_MOLECULAR) {
@@ -548,7 +550,7 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
                 if (r2 < rl2w) nw++;
             }
             for (int q = 0; q < P; ++q) maxsub = std::max(maxsub, cnt[q]);
-            S->work[i] = nw + 32.0;
+            S->work[i] = nw + 72.0;
         }
     }
     const int kmax = std::max(8, d.cutoff_on ? 2 * maxsub + 8 : maxsub + 1);
@@ -557,6 +559,7 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
     HIPCHK(S, dalloc(S, &d.nbc, (size_t)R * np * P));
     HIPCHK(S, dalloc(S, &d.guard, 2 * R));
     HIPCHK(S, dalloc(S, &d.need_build, R));
+    HIPCHK(S, dalloc(S, &d.last_build, 2 * R));
     HIPCHK(S, dalloc(S, &d.err, 4));
     HIPCHK(S, dalloc(S, &d.sync, (size_t)R * 64));
     HIPCHK(S, dalloc(S, &d.xchg, (size_t)R * 3 * np));
@@ -617,7 +620,7 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
 
     // LDS budgets
     const int nblk = (n + BLK - 1) / BLK;
-    S->lds_nb = (size_t)np * 24 + (size_t)nblk * 16;
+    S->lds_nb = (size_t)np * 24 + (size_t)nblk * 16 + (size_t)16 * WBLK * 4;
     S->lds_stage = (size_t)np * 16;
     int dev = 0, maxlds = 0;
     HIPCHK(S, hipGetDevice(&dev));

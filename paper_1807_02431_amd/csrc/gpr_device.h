@@ -29,6 +29,7 @@ constexpr int P = 4;            // lanes per atom in the pair loop (sub-lists by
 constexpr int MAX_OBS = 8;
 constexpr int CHMAX = 4;        // atoms per thread in the integrator mapping
 constexpr int BLK = 8;          // consecutive atoms per bounding sphere in the pair search (a multiple of P)
+constexpr int WBLK = 64;        // LDS ints per wave: the near blocks of one 64-block chunk in the pair search
 constexpr double FIX = 4294967296.0;          // 2^32
 constexpr double FIX_INV = 2.3283064365386963e-10;  // 2^-32
 constexpr float FMAX_FIX = 1.0e9f;             // |F| beyond this counts as unstable
@@ -83,6 +84,7 @@ struct Dev {
     int Kg;                                // capacity of one sub-list, in groups of four
     int *guard;                            // [2][R] displacement guard flags by step parity
     int *need_build;                       // [R]
+    long long *last_build;                 // [2][R] step of the last pair-list build, by step parity
     int *err;                              // [4] error flags
     int *sync;                             // [R][64] per-replica barrier counter and flags (groups > 1)
     float *xchg;                           // [R][3][np] position exchange between a replica's groups
@@ -122,6 +124,7 @@ typedef int gv_i4 __attribute__((ext_vector_type(4)));
 typedef unsigned gv_u2 __attribute__((ext_vector_type(2)));
 typedef float gv_f2 __attribute__((ext_vector_type(2)));
 typedef float gv_f4 __attribute__((ext_vector_type(4)));
+typedef float gv_f3 __attribute__((ext_vector_type(3)));   // 16-byte size and alignment, 12-byte loads
 __device__ __forceinline__ int2 gld(const GPR_GLOBAL int2 *p) { const gv_i2 v = *(const GPR_GLOBAL gv_i2 *)p; return make_int2(v.x, v.y); }
 __device__ __forceinline__ int4 gld(const GPR_GLOBAL int4 *p) { const gv_i4 v = *(const GPR_GLOBAL gv_i4 *)p; return make_int4(v.x, v.y, v.z, v.w); }
 __device__ __forceinline__ uint2 gld(const GPR_GLOBAL uint2 *p) { const gv_u2 v = *(const GPR_GLOBAL gv_u2 *)p; return make_uint2(v.x, v.y); }

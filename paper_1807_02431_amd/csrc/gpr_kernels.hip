@@ -236,9 +236,15 @@ __device__ __forceinline__ float wave16_max(float v)
 // any lane found near); lanes with valid == false take part but own no list.
 // Sub-list (i, q): partners j = q (mod P), j != i, not excluded, |x_i - x_j| < r_list, in
 // ascending order; entry k is the 16-bit word k % 4 of group k / 4; the last group is padded
-// with the dummy atom n.  allpairs: no distance tests (vacuum, no cutoff).
+// with the dummy atom n.  allpairs: no distance tests (vacuum, no cutoff; r_list^2 = inf).
+// Per 64-block chunk the near blocks are listed in the wave's LDS scratch wblk (ascending);
+// their candidates are tested without branches, the outcomes kept as bits (BLK / P per block,
+// 32 blocks per batch), and each lane then writes the entries it keeps, dropping itself and
+// excluded partners at that point.  UNR blocks are read at a time (more registers, fewer
+// exposed LDS latencies); the plain path's pair kernel uses 1 to keep its occupancy.
+template <int UNR>
 __device__ __noinline__ void build_wave(const Dev &S, int r, int i, int q, bool valid, const GPR_LDS gv_f4 *xs,
-                                        const GPR_LDS gv_f4 *sph, bool allpairs)
+                                        const GPR_LDS gv_f4 *sph, GPR_LDS int *wblk, bool allpairs)
 {
     const int n = S.n;
     const size_t stride = (size_t)S.np * P;
@@ -257,14 +263,49 @@ __device__ __noinline__ void build_wave(const Dev &S, int r, int i, int q, bool 
     }
     const float rw = S.rl + sqrtf(wave16_max(d2)) * 1.0001f + 1e-6f;
     const float rl2 = S.rl2;
-    const unsigned long long ex = valid ? gconst(S.excl)[i] : 0ull;
+    // partners to drop: excluded and 1-4 pairs within +-32 of i, and i itself (bit 32)
+    const unsigned long long ex = (valid ? gconst(S.excl)[i] : 0ull) | (1ull << 32);
     const int cap = 4 * S.Kg;
     GPR_GLOBAL unsigned long long *L =
         (GPR_GLOBAL unsigned long long *)gmut(S.nbl) + (size_t)r * S.Kg * stride + (size_t)(valid ? i : 0) * P + q;
     const int lane = threadIdx.x & 63;
     const int nblk = (n + BLK - 1) / BLK;
-    unsigned long long word = 0ull;
+    constexpr int CPB = BLK / P;                                // candidates per block and lane
+    constexpr int BATCH = 64 / CPB;                             // blocks per batch of bits
+    static_assert(BATCH % UNR == 0, "a batch holds whole groups of UNR blocks");
+    unsigned long long word = 0ull, bits = 0ull;
     int cnt = 0;
+    // entries kept in bits, whose blocks are wblk[base ...]; entry cnt is 16-bit word cnt % 4 of
+    // group cnt / 4, and a group is stored once complete
+    auto emit = [&](int base) {
+        __builtin_amdgcn_wave_barrier();
+        while (bits) {
+            int k[UNR], bk[UNR];
+#pragma unroll
+            for (int e = 0; e < UNR; ++e) {
+                k[e] = bits ? __builtin_ctzll(bits) : -1;
+                bits &= bits - 1ull;
+            }
+#pragma unroll
+            for (int e = 0; e < UNR; ++e) bk[e] = wblk[base + (k[e] >= 0 ? k[e] / CPB : 0)];
+#pragma unroll
+            for (int e = 0; e < UNR; ++e) {
+                if (k[e] < 0) break;
+                const int j = bk[e] * BLK + q + (k[e] % CPB) * P;
+                const int off = j - i + 32;
+                if ((unsigned)off < 64u && ((ex >> off) & 1ull)) continue;
+                if (cnt < cap) {
+                    word |= (unsigned long long)j << (16 * (cnt & 3));
+                    if ((cnt & 3) == 3) {
+                        gst(L + (size_t)(cnt >> 2) * stride, word);
+                        word = 0ull;
+                    }
+                }
+                ++cnt;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
     for (int cb = 0; cb < nblk; cb += 64) {
         const int b = cb + lane;
         bool near = b < nblk;
@@ -274,33 +315,49 @@ __device__ __noinline__ void build_wave(const Dev &S, int r, int i, int q, bool 
             const float lim = rw + c.w;
             near = dx * dx + dy * dy + dz * dz < lim * lim;
         }
-        unsigned long long m = __ballot(near);
-        while (m) {
-            const int bb = cb + __builtin_ctzll(m);
-            m &= m - 1ull;
+        const unsigned long long m = __ballot(near);
+        const int cntm = __popcll(m);
+        if (cntm == 0) continue;
+        __builtin_amdgcn_wave_barrier();
+        if (near) wblk[__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u))] = b;
+        __builtin_amdgcn_wave_barrier();
+        int base = 0;
+        for (int k0 = 0; k0 < cntm; k0 += UNR) {
+            int bbs[UNR];
 #pragma unroll
-            for (int t = 0; t < BLK / P; ++t) {
-                const int j = bb * BLK + q + t * P;
-                const int off = j - i;
-                const bool excl = off >= -32 && off < 32 && ((ex >> (off + 32)) & 1ull);
-                bool take = valid && j < n && j != i && !excl;
-                if (!allpairs) {
-                    const gv_f4 pj = xs[min(j, n)];
-                    const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-                    take = take && fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < rl2;
+            for (int u = 0; u < UNR; ++u) {
+                const int v = wblk[min(k0 + u, cntm - 1)];          // read unconditionally: no branch
+                bbs[u] = k0 + u < cntm ? v : -1;
+            }
+            // (x, y, z) only: a 12-byte read leaves no unused destination register that the
+            // compiler could reuse, and so wait for, before the read completes
+            gv_f3 pj[UNR][CPB];
+            const GPR_LDS gv_f3 *x3 = (const GPR_LDS gv_f3 *)xs;
+#pragma unroll
+            for (int u = 0; u < UNR; ++u)
+#pragma unroll
+                for (int t = 0; t < CPB; ++t)
+                    pj[u][t] = x3[bbs[u] >= 0 ? min(bbs[u] * BLK + q + t * P, n) : n];
+            __builtin_amdgcn_sched_barrier(0);                  // keep the reads ahead of the tests
+            unsigned long long tb = 0ull;
+#pragma unroll
+            for (int u = 0; u < UNR; ++u)
+#pragma unroll
+                for (int t = 0; t < CPB; ++t) {
+                    const float dx = pi.x - pj[u][t].x, dy = pi.y - pj[u][t].y, dz = pi.z - pj[u][t].z;
+                    // bitwise, not short-circuit, so that no branch is generated
+                    const unsigned take = (unsigned)valid & (unsigned)(bbs[u] >= 0) &
+                                          (unsigned)(bbs[u] * BLK + q + t * P < n) &
+                                          (unsigned)(fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < rl2);
+                    tb |= (unsigned long long)take << (u * CPB + t);
                 }
-                if (take) {
-                    if (cnt < cap) {
-                        word |= (unsigned long long)j << (16 * (cnt & 3));
-                        if ((cnt & 3) == 3) {
-                            gst(L + (size_t)(cnt >> 2) * stride, word);
-                            word = 0ull;
-                        }
-                    }
-                    ++cnt;
-                }
+            bits |= tb << (((k0 - base) % BATCH) * CPB);
+            if (k0 + UNR - base == BATCH) {
+                emit(base);
+                base += BATCH;
             }
         }
+        emit(base);
     }
     if (!valid) return;
     const int ng = (cnt + 3) >> 2;
@@ -639,15 +696,31 @@ __global__ void __launch_bounds__(1024) k_nonbonded(const Dev *__restrict__ Sp, 
     float4 *xs = (float4 *)lds_raw;
     float2 *pp = (float2 *)(xs + S.np);
     float4 *sph = (float4 *)(pp + S.np);
+    int *wscr = (int *)(sph + (S.n + BLK - 1) / BLK);      // [16][WBLK] build scratch per wave
     __shared__ long long e_acc;
     const int r = r_off + blockIdx.y;
     const int tid = threadIdx.x, nthr = blockDim.x;
     stage_replica(S, r, xs, pp, tid, nthr);
     if (tid == 0) e_acc = 0;
+    // rebuild when forced, when flagged (displacement guard or a new configuration), or on the
+    // steps s with s + 1 a multiple of period, the same steps for every replica: one launch
+    // serves all replicas, so rebuilds that coincide cost one long launch instead of many.
+    // The step of the last build is recorded by step parity (block 0 writes the next step's
+    // slot while the other blocks read this step's) for the persistent path.
     bool rebuild = force_build != 0;
     if (!force_build) {
-        if (S.cutoff_on) rebuild = ((s + 1) % S.period == 0) || S.guard[(s & 1) * S.R + r] != 0;
-        if (blockIdx.x == 0 && tid == 0) S.guard[((s + 1) & 1) * S.R + r] = 0;
+        long long lb = 0;
+        if (S.cutoff_on) {
+            lb = S.last_build[(s & 1) * S.R + r];
+            rebuild = (s + 1) % S.period == 0 || S.guard[(s & 1) * S.R + r] != 0;
+        }
+        if (blockIdx.x == 0 && tid == 0) {
+            S.guard[((s + 1) & 1) * S.R + r] = 0;
+            S.last_build[((s + 1) & 1) * S.R + r] = rebuild ? s : lb;
+        }
+    } else if (blockIdx.x == 0 && tid == 0) {
+        S.last_build[r] = s;
+        S.last_build[S.R + r] = s;
     }
     __syncthreads();
     const int i = blockIdx.x * (nthr / P) + tid / P;
@@ -656,7 +729,8 @@ __global__ void __launch_bounds__(1024) k_nonbonded(const Dev *__restrict__ Sp, 
     if (rebuild) {
         block_spheres(S, xs, sph, tid, nthr);
         __syncthreads();
-        build_wave(S, r, i, q, i < S.n, (const GPR_LDS gv_f4 *)xs, (const GPR_LDS gv_f4 *)sph, !S.cutoff_on);
+        build_wave<1>(S, r, i, q, i < S.n, (const GPR_LDS gv_f4 *)xs, (const GPR_LDS gv_f4 *)sph,
+                   (GPR_LDS int *)wscr + (tid >> 6) * WBLK, !S.cutoff_on);
         if (i < S.n && q == 0) {
             S.xb[b + i] = xs[i].x; S.xb[b + S.np + i] = xs[i].y; S.xb[b + 2 * S.np + i] = xs[i].z;
         }
@@ -802,6 +876,7 @@ __global__ void __launch_bounds__(1024) k_persist(const Dev *__restrict__ Sp, lo
     float *sdl = iml + lmax;                               // [lmax] noise amplitude of own atoms
     float *xbl = sdl + lmax;                               // [3][lmax] own positions at the last list build
     float4 *sph = (float4 *)(xbl + 3 * lmax);              // [nblk]
+    int *wscr = (int *)(sph + (n + BLK - 1) / BLK);        // [16][WBLK] build scratch per wave
     __shared__ int sbuf, bbuf, hbuf;
 
     int r, g;
@@ -841,6 +916,7 @@ __global__ void __launch_bounds__(1024) k_persist(const Dev *__restrict__ Sp, lo
         sdl[l] = a < a1 ? sdv[a] : 0.f;
     }
     bool need = S.need_build[r] != 0;
+    long long lastb = S.last_build[(s0 & 1) * S.R + r];     // step of the last pair-list build
     __syncthreads();
     const bool toy = S.kind == KIND_TOY;
     const BondedPlan bplan = bonded_plan(S, a0, a1);
@@ -887,14 +963,18 @@ __global__ void __launch_bounds__(1024) k_persist(const Dev *__restrict__ Sp, lo
         } else {
             any_hit = __syncthreads_or(hit);
         }
-        if (S.cutoff_on && (need || any_hit || ((s + 1) % S.period == 0))) {
+        // each replica is its own set of workgroups here, so its list is rebuilt when it is
+        // period steps old (or flagged), independently of the other replicas
+        if (S.cutoff_on && (need || any_hit || s - lastb >= S.period)) {
+            lastb = s;
             block_spheres(S, xs, sph, tid, BT);
             __syncthreads();
             for (int L0 = a0 * P; L0 < a1 * P; L0 += BT) {
                 if (L0 + (tid & ~63) >= a1 * P) continue;          // whole wave past the group's atoms
                 const int L = L0 + tid, i = L / P, q = L % P;
                 const bool valid = L < a1 * P;
-                build_wave(S, r, i, q, valid, (const GPR_LDS gv_f4 *)xs, (const GPR_LDS gv_f4 *)sph, false);
+                build_wave<4>(S, r, i, q, valid, (const GPR_LDS gv_f4 *)xs, (const GPR_LDS gv_f4 *)sph,
+                           (GPR_LDS int *)wscr + (tid >> 6) * WBLK, false);
                 if (valid && q == 0) {
                     const int l = i - a0;
                     xbl[l] = xs[i].x; xbl[lmax + l] = xs[i].y; xbl[2 * lmax + l] = xs[i].z;
@@ -990,7 +1070,10 @@ __global__ void __launch_bounds__(1024) k_persist(const Dev *__restrict__ Sp, lo
             xbg[d * np + a] = xbl[d * lmax + l];
         }
     }
-    if (g == 0 && tid == 0 && nsteps > 0) S.need_build[r] = 0;
+    if (g == 0 && tid == 0 && nsteps > 0) {
+        S.need_build[r] = 0;
+        S.last_build[((s0 + nsteps) & 1) * S.R + r] = lastb;
+    }
     if (state_end && g == 0) {
         __syncthreads();
         const int id = state_wg(S, xs, red, &sbuf, tid, BT);
