@@ -1,0 +1,142 @@
+"""GPU edge cases, through the C ABI: the largest systems the LDS-resident kernels take and a
+clean refusal beyond them, workgroups that own no atoms, the smallest replica count, launch
+shapes the device cannot hold, and the degenerate Fleming-Viot check at which every worker
+exits (all are re-copied from the reference walker and the accumulators restart)."""
+import sys
+
+import numpy as np
+import pytest
+
+import gpr_synth as G
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpr():
+    import paper_1807_02431_amd as gpr
+    return gpr
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _force_err(Fg, Fo):
+    return np.abs(Fg - Fo).max() / np.abs(Fo).max()
+
+
+def test_largest_persistent_system():
+    """4,600 atoms (receptor 4,568 + ligand 32 in a 5 nm sphere), 8 replicas: the persistent path
+    splits each replica over 8 workgroups (fewer do not fit in LDS); forces of sampled replicas
+    match the oracle, and both stepping paths give identical bits."""
+    gpr = _gpr()
+    spec = G.round_to_f32(G.receptor_ligand(n_receptor=4568, radius=5.0, n_replicas=8))
+    say("largest persistent system, n =", spec["n_atoms"])
+    runs = []
+    for path in (gpr.PATH_PERSISTENT, gpr.PATH_PLAIN):
+        g = gpr.System(spec, path=path)
+        g.advance(25)
+        runs.append(np.stack([g.get_state(r)[0] for r in range(8)]))
+    assert np.array_equal(runs[0], runs[1])
+    E, F = g.energy_forces()
+    o = oracle.System(dict(spec, n_replicas=2))
+    for r in (0, 7):
+        Uo, Fo = o.eval(runs[0][r])
+        err = _force_err(F[r], Fo)
+        say("replica", r, "force rel err", err)
+        assert err < 1e-5
+        assert abs(E[r] - Uo) <= 1e-5 * abs(Uo)
+
+
+def test_system_beyond_persistent_limit_runs_plain():
+    """5,200 atoms: no split of a replica fits the persistent kernel's LDS, so selecting that
+    path is refused with EINVAL and nothing changes; the plain path still matches the oracle."""
+    gpr = _gpr()
+    spec = G.round_to_f32(G.receptor_ligand(n_receptor=5168, radius=5.2, n_replicas=2))
+    say("beyond persistent limit, n =", spec["n_atoms"])
+    g = gpr.System(spec)
+    with pytest.raises(gpr.GprError) as e:
+        g.set_path(gpr.PATH_PERSISTENT)
+    assert e.value.code == -1
+    g.advance(10)
+    E, F = g.energy_forces()
+    o = oracle.System(spec)
+    q, _ = g.get_state(1)
+    Uo, Fo = o.eval(q)
+    assert _force_err(F[1], Fo) < 1e-5
+
+
+def test_system_too_large_is_refused():
+    """6,500 atoms exceed the LDS of the plain pair kernel too: creation fails with EINVAL."""
+    gpr = _gpr()
+    spec = G.receptor_ligand(n_receptor=6468, radius=5.6, n_replicas=2)
+    say("too large, n =", spec["n_atoms"])
+    with pytest.raises(gpr.GprError) as e:
+        gpr.System(spec)
+    assert e.value.code == -1
+
+
+def test_groups_without_atoms_and_two_replicas():
+    """The 22-atom chain split over 8 workgroups of 64 threads (six of them own no atom) and with
+    2 replicas, the smallest count: positions match the oracle after 100 steps, and the bits
+    equal the plain path's after 100 and after 300 steps."""
+    gpr = _gpr()
+    spec = G.round_to_f32(G.config("chain22", n_replicas=2))
+    say("empty groups, chain22 x 2")
+    a = gpr.System(spec, path=gpr.PATH_PERSISTENT)
+    a.set_launch(64, 8)
+    b = gpr.System(spec, path=gpr.PATH_PLAIN)
+    o = oracle.System(spec)
+    o.step_replicas(100, 0, 2)
+    for steps in (100, 200):
+        a.advance(steps)
+        b.advance(steps)
+        for r in range(2):
+            qa, va = a.get_state(r)
+            qb, vb = b.get_state(r)
+            assert np.array_equal(qa, qb) and np.array_equal(va, vb)
+            if steps == 100:
+                qo, _ = o.get_state(r)
+                assert np.abs(qa - qo).max() < 1e-5 * np.abs(qo).max()
+
+
+def test_impossible_launch_shape_is_refused_and_changes_nothing():
+    gpr = _gpr()
+    spec = G.config("rl2432")
+    g = gpr.System(spec, path=gpr.PATH_PERSISTENT)
+    for bt, grp in ((1024, 1), (100, 4), (1024, 3)):
+        with pytest.raises(gpr.GprError) as e:
+            g.set_launch(bt, grp)
+        assert e.value.code == -1
+    ref = gpr.System(spec, path=gpr.PATH_PERSISTENT)
+    g.advance(20)
+    ref.advance(20)
+    assert np.array_equal(g.get_state(5)[0], ref.get_state(5)[0])
+
+
+@pytest.mark.parametrize("path", [0, 1])
+@pytest.mark.parametrize("seed", [19, 25])
+def test_every_worker_exits_at_a_check(path, seed):
+    """Two replicas started at x = -0.05 on the toy: at the first check of the dephasing the one
+    worker has crossed to x > 0 while the reference walker has not (seeds chosen with the
+    oracle; the crossing margin is > 1e-4).  With no survivor the worker is re-copied from the
+    reference walker and the accumulators restart, as the oracle does."""
+    gpr = _gpr()
+    spec = G.round_to_f32(dict(G.toy2d(n_replicas=2, seed=seed), pos=np.array([[-0.05], [0.0], [0.0]])))
+    say("all workers exit, seed", seed, "path", path)
+    g = gpr.System(spec, path=path)
+    o = oracle.System(spec)
+    for s in (g, o):
+        rc, ev = s.decorrelate(0)
+        assert rc == 0 and ev["to_state"] == 0
+        rc, out = s.dephase(10)
+        assert rc == 1
+    for s in (g, o):
+        q0, v0 = s.get_state(0)
+        q1, v1 = s.get_state(1)
+        assert np.array_equal(q0, q1) and np.array_equal(v0, v1)
+        assert s.accumulators()[0] == 0
+    assert np.abs(g.get_state(0)[0] - o.get_state(0)[0]).max() < 1e-5
+    assert g.simulated_steps() == o.simulated_steps()
