@@ -94,6 +94,7 @@ def lib():
         L.gro_destroy.restype = None
         L.gro_error.restype = C.c_char_p
         L.gro_eval.argtypes = [vp, _PD, _PD, _PD]
+        L.gro_param_grad.argtypes = [vp, _PD, _PD, _PD, _PD, _PD]
         L.gro_energy_forces.argtypes = [vp, C.c_int32, C.c_int32, _PD, _PD]
         L.gro_decorrelate.argtypes = [vp, C.c_int64, C.c_int64, C.POINTER(_Event)]
         L.gro_dephase.argtypes = [vp, C.c_int64, C.POINTER(_Dephase)]
@@ -164,6 +165,7 @@ class System:
         self.n = n
         self.R = int(spec["n_replicas"])
         self.nobs = len(spec.get("obs", []))
+        self.nt = len(spec.get("torsion_k", []) if spec.get("torsion_k") is not None else [])
         s = _Spec()
         s.kind, s.n_atoms, s.n_replicas = int(spec["kind"]), n, self.R
 
@@ -246,6 +248,15 @@ class System:
         U = C.c_double()
         _check(lib().gro_eval(self._h, _pd(q), _pd(F), C.byref(U)), "gro_eval")
         return U.value, F
+
+    def param_grad(self, q):
+        """dU/d(eps, sigma, charge, torsion k) at positions q (Sec. 3.2 force field)."""
+        q = _d(q).reshape(3, self.n)
+        nt = self.nt
+        ge, gs, gq = np.zeros(self.n), np.zeros(self.n), np.zeros(self.n)
+        gk = np.zeros(max(1, nt))
+        _check(lib().gro_param_grad(self._h, _pd(q), _pd(ge), _pd(gs), _pd(gq), _pd(gk)), "gro_param_grad")
+        return dict(epsilon=ge, sigma=gs, charge=gq, torsion_k=gk[:nt])
 
     def energy_forces(self, r0=0, nr=None):
         nr = self.R - r0 if nr is None else nr

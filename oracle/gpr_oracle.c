@@ -337,6 +337,81 @@ int gro_eval(const gro_sys *S, const double *q, double *F, double *U)
     return GRO_OK;
 }
 
+/* ------------------------------------------------------------------ parameter gradient
+ * dU/dtheta at positions q for the per-atom Lennard-Jones eps_i and sigma_i, the charges q_i
+ * and the torsion force constants k_t: the energy terms of eval_molecular differentiated by
+ * hand, term by term over the same pairs.
+ *   eps_ij = sqrt(eps_i eps_j):  d eps_ij / d eps_i = eps_ij / (2 eps_i)     (eps_i > 0)
+ *   sigma_ij = (sigma_i + sigma_j) / 2:  d / d sigma_i = 1/2 d / d sigma_ij, and with
+ *     s = sigma_ij / r,  d/d sigma_ij [4 eps (s^12 - s^6)] = 4 eps (12 s^12 - 6 s^6) / sigma_ij
+ *   Coulomb f q_i q_j g(r), g = 1/r (vacuum, 1-4) or 1/r + k_rf r^2 - c_rf (reaction field):
+ *     d / d q_i = f q_j g(r)
+ *   torsion k (1 + cos(n phi - phi0)):  d / dk = 1 + cos(n phi - phi0)
+ * 1-4 pairs carry their scale factor.  Outputs are overwritten: dU_eps, dU_sig, dU_q [n],
+ * dU_k [number of torsions] (each may be NULL). */
+int gro_param_grad(const gro_sys *S, const double *q, double *dU_eps, double *dU_sig, double *dU_q, double *dU_k)
+{
+    const int n = S->n;
+    if (S->kind != GRO_MOLECULAR) return GRO_EINVAL;
+    double *ge = (double *)calloc((size_t)n, sizeof(double));
+    double *gs = (double *)calloc((size_t)n, sizeof(double));
+    double *gq = (double *)calloc((size_t)n, sizeof(double));
+    if (!ge || !gs || !gq) { free(ge); free(gs); free(gq); return GRO_ENOMEM; }
+
+    /* one pair: scale * [LJ + Coulomb with kernel g] */
+    #define PAIR_GRAD(I, J, R, G, SCALE)                                                   \
+        do {                                                                               \
+            const double sij = 0.5 * (S->sigma[I] + S->sigma[J]);                          \
+            const double eij = sqrt(S->eps[I] * S->eps[J]);                                \
+            const double s6 = pow(sij / (R), 6.0), s12 = s6 * s6;                          \
+            const double ulj = 4.0 * eij * (s12 - s6);                                     \
+            const double dsig = 0.5 * 4.0 * eij * (12.0 * s12 - 6.0 * s6) / sij;           \
+            ge[I] += (SCALE) * ulj / (2.0 * S->eps[I]);                                    \
+            ge[J] += (SCALE) * ulj / (2.0 * S->eps[J]);                                    \
+            gs[I] += (SCALE) * dsig;                                                       \
+            gs[J] += (SCALE) * dsig;                                                       \
+            gq[I] += (SCALE) * COULOMB_F * S->charge[J] * (G);                             \
+            gq[J] += (SCALE) * COULOMB_F * S->charge[I] * (G);                             \
+        } while (0)
+
+    for (int pp = 0; pp < S->np; pp++) {
+        int i = S->p14[2 * pp], j = S->p14[2 * pp + 1];
+        double pi_[3], pj[3], d[3];
+        getp(q, n, i, pi_); getp(q, n, j, pj);
+        for (int k = 0; k < 3; k++) d[k] = pi_[k] - pj[k];
+        const double r = sqrt(dot3(d, d));
+        PAIR_GRAD(i, j, r, 1.0 / r, S->scale14);
+    }
+    const double rc = S->cutoff;
+    double krf = 0.0, crf = 0.0;
+    if (rc > 0.0) {
+        krf = (S->eps_rf - 1.0) / ((2.0 * S->eps_rf + 1.0) * rc * rc * rc);
+        crf = 1.0 / rc + krf * rc * rc;
+    }
+    for (int i = 0; i < n; i++) {
+        for (int j = i + 1; j < n; j++) {
+            if (S->skip[(size_t)i * n + j]) continue;
+            double pi_[3], pj[3], d[3];
+            getp(q, n, i, pi_); getp(q, n, j, pj);
+            for (int k = 0; k < 3; k++) d[k] = pi_[k] - pj[k];
+            const double r2 = dot3(d, d);
+            if (rc > 0.0 && !(r2 < rc * rc)) continue;
+            const double r = sqrt(r2);
+            const double g = rc > 0.0 ? 1.0 / r + krf * r2 - crf : 1.0 / r;
+            PAIR_GRAD(i, j, r, g, 1.0);
+        }
+    }
+    #undef PAIR_GRAD
+    if (dU_k)
+        for (int t = 0; t < S->nt; t++)
+            dU_k[t] = 1.0 + cos((double)S->t_n[t] * dihedral(q, n, S->tor + 4 * t) - S->t_p0[t]);
+    if (dU_eps) memcpy(dU_eps, ge, sizeof(double) * (size_t)n);
+    if (dU_sig) memcpy(dU_sig, gs, sizeof(double) * (size_t)n);
+    if (dU_q) memcpy(dU_q, gq, sizeof(double) * (size_t)n);
+    free(ge); free(gs); free(gq);
+    return GRO_OK;
+}
+
 /* ------------------------------------------------------------------ replica access */
 static double *Q(const gro_sys *S, int r) { return S->q + (size_t)r * 3 * S->n; }
 static double *Vv(const gro_sys *S, int r) { return S->v + (size_t)r * 3 * S->n; }

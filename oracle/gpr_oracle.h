@@ -100,6 +100,8 @@ const char *gro_error(void);
 
 /* potential energy and forces at arbitrary positions q[3][n] (SoA) */
 int  gro_eval(const gro_sys *S, const double *q, double *F, double *U);
+/* dU/d(eps_i, sigma_i, q_i, torsion k_t) at positions q[3][n] (molecular systems, eps_i > 0) */
+int  gro_param_grad(const gro_sys *S, const double *q, double *dU_eps, double *dU_sig, double *dU_q, double *dU_k);
 int  gro_energy_forces(const gro_sys *S, int32_t r0, int32_t nr, double *E, double *F);
 int  gro_decorrelate(gro_sys *S, int64_t t_corr, int64_t max_steps, gro_event *ev);
 int  gro_dephase(gro_sys *S, int64_t max_steps, gro_dephase_result *o);
