@@ -120,6 +120,38 @@ def cpu_baseline(spec, seconds=15.0):
                 atom_steps_per_s=R * steps * spec["n_atoms"] / dt)
 
 
+def differentiation_bench(spec, iters):
+    """Forward (energy and forces) + backward (position and force-field parameter gradients) of
+    all replicas through the device-pointer entry points, one batch per evaluation."""
+    import torch
+    import paper_1807_02431_amd as gpr
+    R, n = spec["n_replicas"], spec["n_atoms"]
+    s = gpr.System(spec, stream=torch.cuda.current_stream())
+    s.advance(20)
+    x = torch.tensor(np.stack([s.get_state(r)[0] for r in range(R)]), dtype=torch.float32, device="cuda")
+    U = torch.empty(R, dtype=torch.float64, device="cuda")
+    w = torch.ones(R, dtype=torch.float64, device="cuda")
+    dx = torch.empty_like(x)
+    ge, gs, gq = (torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(3))
+    gk = torch.empty(max(1, s.nt), dtype=torch.float64, device="cuda")
+
+    def once():
+        s.energy_forces_dev(x.data_ptr(), U.data_ptr(), 0)
+        s.energy_backward_dev(w.data_ptr(), dx.data_ptr(), ge.data_ptr(), gs.data_ptr(), gq.data_ptr(), gk.data_ptr())
+
+    for _ in range(3):
+        once()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        once()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / iters
+    return dict(batch_evals_per_s=1.0 / dt, replica_evals_per_s=R / dt, ms_per_batch_eval=1e3 * dt,
+                iters=iters, note="forward = energies + forces of all replicas (pair lists rebuilt); "
+                "backward = dU/dx and dU/d(eps, sigma, q, torsion k) summed over replicas")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,6 +159,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-diff", action="store_true", help="skip the differentiation measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 256 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -180,6 +213,11 @@ def main():
                      ms_per_step=1e3 * t_pl / args.steps, launches_per_step=3,
                      pair_kernel_us=1e3 * nb_ms / max(nb_n, 1))
 
+    diff = None
+    if not args.no_diff:
+        print("# differentiation: forward + backward", file=sys.stderr, flush=True)
+        diff = differentiation_bench(spec, 50)
+
     cpu = None if args.no_cpu else cpu_baseline(spec)
 
     steps_per_launch = args.steps / max(klaunch, 1)
@@ -211,6 +249,7 @@ def main():
                      "steps_per_launch": steps_per_launch, "flop_per_replica_step": frs,
                      "in_cutoff_pairs_per_replica": pairs},
         "cpu_baseline": cpu,
+        "differentiation": diff,
     }
     print(json.dumps(out), flush=True)
 

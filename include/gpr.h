@@ -225,6 +225,39 @@ gpr_status gpr_set_launch(gpr_system *sys, int32_t block_threads, int32_t groups
  * Forces are the 64-bit fixed-point accumulators (2^-32 kJ/mol/nm) converted exactly. */
 gpr_status gpr_energy_forces(gpr_system *sys, int32_t r0, int32_t nr, double *energy, double *forces);
 
+/* ---------------------------------------------------------------- differentiation
+ * The potential energy U_r(x_r; theta) of every replica as a function of its positions and of
+ * the force-field parameters theta = (epsilon_i, sigma_i, charge_i per atom, k_t per torsion),
+ * with the terms and combination rules of the descriptor (Sec. 3.2 engine requirement: V(q)
+ * and its gradient).  dU/dx = -F comes with the forces; the parameter gradient is a second
+ * pass over the same terms.  For callers whose tensors live on the GPU (an autograd binding):
+ * *_dev pointers are device memory, written on the system's stream, and the call returns once
+ * the stream has finished. */
+
+/* Replaces epsilon, sigma, charge ([n_atoms], caller's atom order) and the torsion force
+ * constants ([n_torsions], caller's torsion order); a NULL array keeps its current values.
+ * Re-evaluates the forces of every replica at its current positions (the integrator carries
+ * them from step to step).  Host buffers.  EINVAL for a toy system, epsilon or sigma < 0, or a
+ * non-finite value (nothing is changed then).  Meant for use between the Gen.ParRep calls. */
+gpr_status gpr_set_params(gpr_system *sys, const double *epsilon, const double *sigma, const double *charge,
+                          const double *torsion_k);
+
+/* Sets the positions of all replicas from x_dev (float, [n_replicas][3][n_atoms] SoA, device),
+ * rebuilds their pair lists and writes energy_dev (double [n_replicas]) and forces_dev (float
+ * [n_replicas][3][n_atoms]); either output may be NULL.  Velocities are kept.  EDEVICE if a pair
+ * list overflows its capacity. */
+gpr_status gpr_energy_forces_dev(gpr_system *sys, const float *x_dev, double *energy_dev, float *forces_dev);
+
+/* Backward pass at the replicas' current positions, weighted by w_dev (double [n_replicas],
+ * device): d_x[r] = w[r] dU_r/dx_r = -w[r] F_r (float [n_replicas][3][n_atoms]) and the
+ * parameter gradient sum_r w[r] dU_r/dtheta into d_epsilon, d_sigma, d_charge (double
+ * [n_atoms]) and d_torsion_k (double [n_torsions], caller's torsion order); device buffers, each
+ * may be NULL.  Parameter sums are taken in 2^-32 fixed point, so they do not depend on the order
+ * of the terms.  EINVAL for a toy system (when a parameter output is requested) or when an
+ * epsilon is 0 and d_epsilon is requested (sqrt(eps_i eps_j) has no derivative there). */
+gpr_status gpr_energy_backward_dev(gpr_system *sys, const double *w_dev, float *d_x, double *d_epsilon,
+                                   double *d_sigma, double *d_charge, double *d_torsion_k);
+
 /* ---------------------------------------------------------------- Gen.ParRep steps (Sec. 2.4) */
 /* Transient propagation of the reference walker (replica 0), Sec. 2.4 step 1, followed by a
  * residence of t_corr_steps in the state reached.  Steps replica 0 with a state test every

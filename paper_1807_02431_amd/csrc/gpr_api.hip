@@ -38,6 +38,11 @@ struct gpr_system {
     int groups = 1;            // workgroups per replica on the persistent path
     Split split{};             // their atom ranges
     std::vector<double> work;  // per-atom work estimate that places the ranges
+    // force-field parameters as the caller gave them (gpr_set_params rewrites the device copies)
+    std::vector<double> mass_h, eps_h, sig_h, q_h, tor_k_h, tor_phi0_h;
+    std::vector<int> tor_n_h, tor_order, p14_order;   // sorted term -> caller's index
+    std::vector<int2> p14_h;
+    double scale14 = 0.0;
     int max_coresident = 0;    // persistent-kernel workgroups that fit on the device at once
     int n = 0, R = 0, np = 0, kind = 0, nobs = 0;
     int t_gr = 1, tcd = 1, tcp = 1;
@@ -215,6 +220,51 @@ static size_t persist_lds(int n, int np, const Split &sp)
     const int nblk = (n + BLK - 1) / BLK;
     return (size_t)3 * lmax * 8 + (MAX_OBS * 8 + 8) * 8 + MAX_OBS * 8 + (size_t)np * 16 + (size_t)np * 8 +
            (size_t)8 * lmax * 4 + (size_t)nblk * 16 + (size_t)16 * WBLK * 4;
+}
+
+// ------------------------------------------------------------------ force-field parameters
+// Device copies of the per-atom parameters (sigma/2, 2 sqrt(eps), q sqrt(f), 1/m), the torsion
+// parameters (k, cos phi0, sin phi0, n) and the 1-4 pair parameters (sigma_ij, 4 eps_ij s14,
+// f q_i q_j s14) in the sorted term order, and 1/(2 eps_i), from the host copies.
+static hipError_t write_params(gpr_system *S)
+{
+    const int n = S->n, np = S->np;
+    Dev &d = S->d;
+    const bool mol = S->kind == GPR_KIND_MOLECULAR;
+    std::vector<float4> prm(np, make_float4(0, 0, 0, 0));
+    std::vector<double> inv2eps(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        const double sig = mol ? S->sig_h[i] : 0.0, eps = mol ? S->eps_h[i] : 0.0, q = mol ? S->q_h[i] : 0.0;
+        prm[i] = make_float4((float)(0.5 * sig), (float)(2.0 * std::sqrt(eps)), (float)(q * std::sqrt(COULOMB_F)),
+                             (float)(1.0 / S->mass_h[i]));
+        inv2eps[i] = eps > 0 ? 0.5 / eps : INFINITY;
+    }
+    hipError_t e = hipMemcpyAsync((void *)d.prm, prm.data(), sizeof(float4) * np, hipMemcpyHostToDevice, S->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync((void *)d.inv2eps, inv2eps.data(), sizeof(double) * n, hipMemcpyHostToDevice, S->stream);
+    const Topo &T = d.tp;
+    if (e == hipSuccess && mol && T.nt) {
+        std::vector<float4> p(T.nt);
+        for (int k = 0; k < T.nt; ++k) {
+            const int t = S->tor_order[k];
+            p[k] = make_float4((float)S->tor_k_h[t], (float)std::cos(S->tor_phi0_h[t]), (float)std::sin(S->tor_phi0_h[t]),
+                               (float)S->tor_n_h[t]);
+        }
+        e = hipMemcpyAsync((void *)T.t_p, p.data(), sizeof(float4) * T.nt, hipMemcpyHostToDevice, S->stream);
+    }
+    if (e == hipSuccess && mol && T.n14) {
+        std::vector<float4> p(T.n14);
+        for (int k = 0; k < T.n14; ++k) {
+            const int2 ij = S->p14_h[S->p14_order[k]];
+            const double sij = 0.5 * (S->sig_h[ij.x] + S->sig_h[ij.y]);
+            const double eij = std::sqrt(S->eps_h[ij.x] * S->eps_h[ij.y]);
+            p[k] = make_float4((float)sij, (float)(4.0 * eij * S->scale14),
+                               (float)(COULOMB_F * S->q_h[ij.x] * S->q_h[ij.y] * S->scale14), 0.f);
+        }
+        e = hipMemcpyAsync((void *)T.p_p, p.data(), sizeof(float4) * T.n14, hipMemcpyHostToDevice, S->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
+    return e;
 }
 
 // ------------------------------------------------------------------ launches
@@ -478,6 +528,7 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
                                    (float)std::sin(D->torsion_phi0[t]), (float)D->torsion_n[t]);
             }
             T.nt = D->n_torsions;
+            S->tor_order = order;
             HIPCHK(S, upload(S, (int4 **)&T.t_ijkl, q)); HIPCHK(S, upload(S, (float4 **)&T.t_p, p));
             HIPCHK(S, upload(S, (int **)&T.t_start, start));
         }
@@ -508,6 +559,7 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
                                    (float)(COULOMB_F * D->charge[i] * D->charge[j] * D->scale14), 0.f);
             }
             T.n14 = D->n_pairs14;
+            S->p14_order = order;
             HIPCHK(S, upload(S, (int2 **)&T.p_ij, ij)); HIPCHK(S, upload(S, (float4 **)&T.p_p, p));
             HIPCHK(S, upload(S, (int **)&T.p_start, start));
         }
@@ -608,6 +660,30 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
     d.key0 = (uint32_t)D->seed;
     d.key1 = (uint32_t)(D->seed >> 32);
     d.t_gr = D->t_gr;
+    // force-field parameters kept on the host, device buffers of the parameter gradient
+    S->mass_h.assign(D->mass, D->mass + n);
+    if (D->kind == GPR_KIND_MOLECULAR) {
+        S->eps_h.assign(D->epsilon, D->epsilon + n);
+        S->sig_h.assign(D->sigma, D->sigma + n);
+        S->q_h.assign(D->charge, D->charge + n);
+        S->tor_k_h.assign(D->torsion_k, D->torsion_k + D->n_torsions);
+        S->tor_phi0_h.assign(D->torsion_phi0, D->torsion_phi0 + D->n_torsions);
+        S->tor_n_h.assign(D->torsion_n, D->torsion_n + D->n_torsions);
+        for (int t = 0; t < D->n_pairs14; ++t)
+            S->p14_h.push_back(make_int2(D->pair14_atoms[2 * t], D->pair14_atoms[2 * t + 1]));
+        S->scale14 = D->scale14;
+    }
+    d.scale14 = (float)D->scale14;
+    d.sqrt_f = std::sqrt(COULOMB_F);
+    HIPCHK(S, dalloc(S, &d.gacc, (size_t)3 * np + std::max(1, d.tp.nt)));
+    {
+        std::vector<double> inv2eps(n, 0.0);
+        HIPCHK(S, upload(S, (double **)&d.inv2eps, inv2eps));
+        std::vector<int> orig(S->tor_order);
+        if (orig.empty()) orig.push_back(0);
+        HIPCHK(S, upload(S, (int **)&d.tor_orig, orig));
+    }
+    HIPCHK(S, write_params(S));
     HIPCHK(S, upload(S, &S->d_dev, std::vector<Dev>(1, d)));
 
     // scratch for the per-check bookkeeping
@@ -629,6 +705,7 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
     if ((int)S->lds_nb > maxlds || (int)S->lds_stage > maxlds)
         return fail(S, GPR_EINVAL, "system too large for the LDS-staged pair kernel");
     HIPCHK(S, hipFuncSetAttribute((const void *)k_nonbonded, hipFuncAttributeMaxDynamicSharedMemorySize, (int)S->lds_nb));
+    HIPCHK(S, hipFuncSetAttribute((const void *)k_grad_nb, hipFuncAttributeMaxDynamicSharedMemorySize, (int)S->lds_nb));
     HIPCHK(S, hipFuncSetAttribute((const void *)k_obs, hipFuncAttributeMaxDynamicSharedMemorySize, (int)S->lds_stage));
     HIPCHK(S, hipFuncSetAttribute((const void *)k_state, hipFuncAttributeMaxDynamicSharedMemorySize, (int)S->lds_stage));
     {
@@ -861,6 +938,81 @@ extern "C" gpr_status gpr_energy_forces(gpr_system *S, int32_t r0, int32_t nr, d
                 for (int i = 0; i < S->n; ++i)
                     forces[((size_t)k * 3 + c) * S->n + i] = (double)F[((size_t)k * 3 + c) * S->np + i] * FIX_INV;
     }
+    return GPR_OK;
+}
+
+extern "C" gpr_status gpr_set_params(gpr_system *S, const double *epsilon, const double *sigma, const double *charge,
+                                     const double *torsion_k)
+{
+    if (!S) return fail(nullptr, GPR_EINVAL, "NULL system");
+    if (S->kind != GPR_KIND_MOLECULAR) return fail(S, GPR_EINVAL, "force-field parameters need a molecular system");
+    const int n = S->n, nt = (int)S->tor_k_h.size();
+    for (int i = 0; i < n; ++i) {
+        if (epsilon && !(epsilon[i] >= 0 && std::isfinite(epsilon[i]))) return fail(S, GPR_EINVAL, "epsilon < 0 or not finite");
+        if (sigma && !(sigma[i] >= 0 && std::isfinite(sigma[i]))) return fail(S, GPR_EINVAL, "sigma < 0 or not finite");
+        if (charge && !std::isfinite(charge[i])) return fail(S, GPR_EINVAL, "charge not finite");
+    }
+    for (int t = 0; t < nt; ++t)
+        if (torsion_k && !std::isfinite(torsion_k[t])) return fail(S, GPR_EINVAL, "torsion k not finite");
+    if (epsilon) S->eps_h.assign(epsilon, epsilon + n);
+    if (sigma) S->sig_h.assign(sigma, sigma + n);
+    if (charge) S->q_h.assign(charge, charge + n);
+    if (torsion_k) S->tor_k_h.assign(torsion_k, torsion_k + nt);
+    HIPCHK(S, write_params(S));
+    // the forces the integrator carries must belong to the new parameters
+    gpr_status rc = launch_forces(S, 0, S->R, -1, 1, 0, 1);
+    if (rc) return rc;
+    HIPCHK(S, hipStreamSynchronize(S->stream));
+    return GPR_OK;
+}
+
+extern "C" gpr_status gpr_energy_forces_dev(gpr_system *S, const float *x_dev, double *energy_dev, float *forces_dev)
+{
+    if (!S) return fail(nullptr, GPR_EINVAL, "NULL system");
+    if (!x_dev) return fail(S, GPR_EINVAL, "NULL positions");
+    const int n = S->n, np = S->np, R = S->R;
+    HIPCHK(S, hipMemcpy2DAsync(S->d.x, sizeof(float) * np, x_dev, sizeof(float) * n, sizeof(float) * n, (size_t)3 * R,
+                               hipMemcpyDeviceToDevice, S->stream));
+    gpr_status rc = launch_forces(S, 0, R, -1, 1, 0, 1);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_unfix_out, dim3((n + 255) / 256, R), dim3(256), 0, S->stream, S->d_dev, energy_dev, forces_dev);
+    LAUNCHCHK(S);
+    int err[4];
+    HIPCHK(S, hipMemcpyAsync(err, S->d.err, sizeof err, hipMemcpyDeviceToHost, S->stream));
+    HIPCHK(S, hipStreamSynchronize(S->stream));
+    if (err[ERR_LIST]) return fail(S, GPR_EDEVICE, "pair-list capacity exceeded");
+    return GPR_OK;
+}
+
+extern "C" gpr_status gpr_energy_backward_dev(gpr_system *S, const double *w_dev, float *d_x, double *d_eps,
+                                              double *d_sigma, double *d_charge, double *d_torsion_k)
+{
+    if (!S) return fail(nullptr, GPR_EINVAL, "NULL system");
+    if (!w_dev) return fail(S, GPR_EINVAL, "NULL weights");
+    const bool params = d_eps || d_sigma || d_charge || d_torsion_k;
+    if (params && S->kind != GPR_KIND_MOLECULAR) return fail(S, GPR_EINVAL, "force-field parameters need a molecular system");
+    if (d_eps)
+        for (double e : S->eps_h)
+            if (!(e > 0)) return fail(S, GPR_EINVAL, "the epsilon gradient needs every epsilon > 0");
+    const int n = S->n, np = S->np, R = S->R, nt = S->d.tp.nt, n14 = S->d.tp.n14;
+    if (d_x) {
+        hipLaunchKernelGGL(k_weighted_dx, dim3((n + 255) / 256, R), dim3(256), 0, S->stream, S->d_dev, w_dev, d_x);
+        LAUNCHCHK(S);
+    }
+    if (params) {
+        HIPCHK(S, hipMemsetAsync(S->d.gacc, 0, sizeof(long long) * ((size_t)3 * np + std::max(1, nt)), S->stream));
+        hipLaunchKernelGGL(k_grad_nb, dim3((n * P + 1023) / 1024, R), dim3(1024), S->lds_nb, S->stream, S->d_dev, w_dev);
+        LAUNCHCHK(S);
+        const int nterm = std::max(nt, n14);
+        if (nterm > 0) {
+            hipLaunchKernelGGL(k_grad_terms, dim3((nterm + 255) / 256, R), dim3(256), 0, S->stream, S->d_dev, w_dev);
+            LAUNCHCHK(S);
+        }
+        hipLaunchKernelGGL(k_grad_finish, dim3((std::max(n, nt) + 255) / 256), dim3(256), 0, S->stream, S->d_dev, d_eps,
+                           d_sigma, d_charge, d_torsion_k);
+        LAUNCHCHK(S);
+    }
+    HIPCHK(S, hipStreamSynchronize(S->stream));
     return GPR_OK;
 }
 

@@ -98,6 +98,12 @@ struct Dev {
     const ObsDesc *obs;                    // [MAX_OBS], device memory
     const StateDesc *st;                   // device memory
     Topo tp;
+    // force-field parameter gradient (molecular systems)
+    long long *gacc;                       // [3][np] + [nt]: fixed-point sums for eps, sigma, charge, torsion k
+    const double *inv2eps;                 // [n] 1 / (2 eps_i)
+    const int *tor_orig;                   // [nt] caller's index of the k-th torsion in sorted order
+    float scale14;
+    double sqrt_f;                         // square root of the Coulomb constant
     float h, c1, rc2, rl, rl2, krf, crf, half_skin2;
     int cutoff_on, period;
     uint32_t key0, key1;
@@ -249,6 +255,30 @@ __device__ __forceinline__ float term_angle(float3 pi, float3 pj, float3 pk, flo
     fk = make_float3(a * (cw * wx - ux), a * (cw * wy - uy), a * (cw * wz - uz));
     return 0.5f * p.y * dth * dth;
 }
+// cos(n phi - phi0) for p = (k, cos phi0, sin phi0, n), by the same algebra as term_torsion
+__device__ __forceinline__ float torsion_cos(float3 pi, float3 pj, float3 pk, float3 pl, float4 p)
+{
+    const float b1x = pj.x - pi.x, b1y = pj.y - pi.y, b1z = pj.z - pi.z;
+    const float b2x = pk.x - pj.x, b2y = pk.y - pj.y, b2z = pk.z - pj.z;
+    const float b3x = pl.x - pk.x, b3y = pl.y - pk.y, b3z = pl.z - pk.z;
+    const float n1x = b1y * b2z - b1z * b2y, n1y = b1z * b2x - b1x * b2z, n1z = b1x * b2y - b1y * b2x;
+    const float n2x = b2y * b3z - b2z * b3y, n2y = b2z * b3x - b2x * b3z, n2z = b2x * b3y - b2y * b3x;
+    const float lb2sq = b2x * b2x + b2y * b2y + b2z * b2z;
+    const float lb2 = lb2sq * __builtin_amdgcn_rsqf(lb2sq);
+    const float xx = n1x * n2x + n1y * n2y + n1z * n2z;
+    const float yy = lb2 * (b1x * n2x + b1y * n2y + b1z * n2z);
+    const float ih = __builtin_amdgcn_rsqf(xx * xx + yy * yy);
+    const float c = xx * ih, sn = yy * ih;
+    float C = 1.0f, Sn = 0.0f;
+    const int nm = (int)p.w;
+    for (int m = 0; m < nm; ++m) {
+        const float C2 = C * c - Sn * sn;
+        Sn = C * sn + Sn * c;
+        C = C2;
+    }
+    return C * p.y + Sn * p.z;
+}
+
 // k (1 + cos(n phi - phi0)) with p = (k, cos phi0, sin phi0, n): cos phi and sin phi come from the
 // two projections that define the dihedral, cos n phi and sin n phi by repeated complex
 // multiplication, so no inverse or direct trigonometric function is evaluated.

@@ -32,6 +32,11 @@ __global__ void k_obs(const Dev *__restrict__ Sp, int r_off, int mode, double *o
 __global__ void k_state(const Dev *__restrict__ Sp, int r_off);
 __global__ void k_persist(const Dev *__restrict__ Sp, long long s0, int nsteps, int t0, int sample, int state_end,
                           Split sp, int nrep);
+__global__ void k_grad_nb(const Dev *__restrict__ Sp, const double *w);
+__global__ void k_grad_terms(const Dev *__restrict__ Sp, const double *w);
+__global__ void k_grad_finish(const Dev *__restrict__ Sp, double *d_eps, double *d_sigma, double *d_charge, double *d_tk);
+__global__ void k_unfix_out(const Dev *__restrict__ Sp, double *energy, float *forces);
+__global__ void k_weighted_dx(const Dev *__restrict__ Sp, const double *w, float *dx);
 __global__ void k_check(const Dev *__restrict__ Sp, int mode, long long s, int omega, int nrep, long long nsamp, int check_index,
                         Status *st, int *donor, int *surv, long long *fec);
 __global__ void k_clone(const Dev *__restrict__ Sp, const int *donor, int acc_mode);

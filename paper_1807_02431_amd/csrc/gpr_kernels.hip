@@ -805,6 +805,147 @@ __global__ void __launch_bounds__(256) k_state(const Dev *__restrict__ Sp, int r
     if (threadIdx.x == 0) S.state[r] = id;
 }
 
+// ================================================================== force-field parameter gradient
+// dU_r/dtheta for theta = (eps_i, sigma_i, q_i, torsion k_t), weighted by w[r] and summed over
+// the replicas in 2^-32 fixed point (gacc).  With eps_ij = sqrt(eps_i eps_j), sigma_ij =
+// (sigma_i + sigma_j)/2, s = sigma_ij / r and Coulomb kernel g(r):
+//   dU/deps_i   = 1/(2 eps_i) sum_j 4 eps_ij (s^12 - s^6)
+//   dU/dsigma_i = sum_j 1/2 4 eps_ij (12 s^12 - 6 s^6) / sigma_ij
+//   dU/dq_i     = sqrt(f) sum_j (q_j sqrt(f)) g(r)
+//   dU/dk_t     = 1 + cos(n phi - phi0)
+// the constant factors 1/(2 eps_i) and sqrt(f) applied in k_grad_finish.  Pair sums run over
+// the full pair lists (every partner of i in i's own sub-lists), so each atom's sums are
+// complete without scattering to j; 1-4 pairs (scaled) and torsions come one term per thread.
+
+// nonbonded pairs of replicas r_off + blockIdx.y at their current positions and pair lists
+__global__ void __launch_bounds__(1024) k_grad_nb(const Dev *__restrict__ Sp, const double *w)
+{
+    const Dev &S = *Sp;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    float4 *xs = (float4 *)lds_raw;
+    float2 *pp = (float2 *)(xs + S.np);
+    const int r = blockIdx.y;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    stage_replica(S, r, xs, pp, tid, nthr);
+    __syncthreads();
+    const int i = blockIdx.x * (nthr / P) + tid / P;
+    const int q = tid % P;
+    float se = 0.f, ss = 0.f, sq = 0.f;
+    if (i < S.n) {
+        const size_t stride = (size_t)S.np * P;
+        const GPR_GLOBAL uint2 *L = gconst(S.nbl) + (size_t)r * S.Kg * stride + (size_t)i * P + q;
+        const int ng = gconst(S.nbc)[(size_t)r * stride + (size_t)i * P + q];
+        const float4 pi = xs[i];
+        const float2 ppi = pp[i];
+        const float rc2 = S.rc2, krf = S.krf, crf = S.crf;
+        for (int g = 0; g < ng; ++g) {
+            const uint2 wv = gld(L + (size_t)g * stride);
+            const int jj[4] = {(int)(wv.x & 0xFFFF), (int)(wv.x >> 16), (int)(wv.y & 0xFFFF), (int)(wv.y >> 16)};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float4 pj = xs[jj[k]];
+                const float2 ppj = pp[jj[k]];
+                const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+                const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                const float ri = __builtin_amdgcn_rsqf(r2);
+                const float sg = ppi.x + ppj.x;
+                const float t = sg * ri;
+                const float s2 = t * t;
+                const float s6 = s2 * s2 * s2, s12 = s6 * s6;
+                const float e4 = ppi.y * ppj.y;
+                const bool in = r2 < rc2;
+                se += in ? e4 * (s12 - s6) : 0.0f;
+                ss += in ? 0.5f * e4 * (12.0f * s12 - 6.0f * s6) * __builtin_amdgcn_rcpf(sg) : 0.0f;
+                sq += in ? pj.w * (ri + krf * r2 - crf) : 0.0f;
+            }
+        }
+    }
+    se = quad_sum(se);
+    ss = quad_sum(ss);
+    sq = quad_sum(sq);
+    if (i < S.n && q == 0) {
+        const double wr = w[r];
+        unsigned long long *G = (unsigned long long *)S.gacc;
+        atomicAdd(G + i, (unsigned long long)fix_d(wr * se));
+        atomicAdd(G + S.np + i, (unsigned long long)fix_d(wr * ss));
+        atomicAdd(G + 2 * S.np + i, (unsigned long long)fix_d(wr * sq));
+    }
+}
+
+// 1-4 pairs (no cutoff, vacuum Coulomb, scaled) and torsions of replica blockIdx.y
+__global__ void __launch_bounds__(256) k_grad_terms(const Dev *__restrict__ Sp, const double *w)
+{
+    const Dev &S = *Sp;
+    const Topo &T = S.tp;
+    const int r = blockIdx.y;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const double wr = w[r];
+    const PosGlob pos{gconst(S.x) + (size_t)r * 3 * S.np, S.np};
+    unsigned long long *G = (unsigned long long *)S.gacc;
+    if (t < T.n14) {
+        const int2 ij = gld(gconst(T.p_ij) + t);
+        const float4 a = gld(gconst(S.prm) + ij.x), b = gld(gconst(S.prm) + ij.y);
+        const float3 xa = pos(ij.x), xb = pos(ij.y);
+        const float dx = xa.x - xb.x, dy = xa.y - xb.y, dz = xa.z - xb.z;
+        const float ri = __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
+        const float sg = a.x + b.x, tt = sg * ri, s2 = tt * tt, s6 = s2 * s2 * s2, s12 = s6 * s6;
+        const float e4 = a.y * b.y, sc = S.scale14;
+        const double ulj = (double)(sc * e4 * (s12 - s6));
+        const double dsg = (double)(sc * 0.5f * e4 * (12.0f * s12 - 6.0f * s6) * __builtin_amdgcn_rcpf(sg));
+        atomicAdd(G + ij.x, (unsigned long long)fix_d(wr * ulj));
+        atomicAdd(G + ij.y, (unsigned long long)fix_d(wr * ulj));
+        atomicAdd(G + S.np + ij.x, (unsigned long long)fix_d(wr * dsg));
+        atomicAdd(G + S.np + ij.y, (unsigned long long)fix_d(wr * dsg));
+        atomicAdd(G + 2 * S.np + ij.x, (unsigned long long)fix_d(wr * (double)(sc * b.z * ri)));
+        atomicAdd(G + 2 * S.np + ij.y, (unsigned long long)fix_d(wr * (double)(sc * a.z * ri)));
+    }
+    if (t < T.nt) {
+        const int4 q = gld(gconst(T.t_ijkl) + t);
+        const float ca = torsion_cos(pos(q.x), pos(q.y), pos(q.z), pos(q.w), gld(gconst(T.t_p) + t));
+        atomicAdd(G + 3 * S.np + t, (unsigned long long)fix_d(wr * (double)(1.0f + ca)));
+    }
+}
+
+__global__ void __launch_bounds__(256) k_grad_finish(const Dev *__restrict__ Sp, double *d_eps, double *d_sigma,
+                                                     double *d_charge, double *d_tk)
+{
+    const Dev &S = *Sp;
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const double sqrt_f = S.sqrt_f;
+    if (a < S.n) {
+        if (d_eps) d_eps[a] = unfix_d(S.gacc[a]) * S.inv2eps[a];
+        if (d_sigma) d_sigma[a] = unfix_d(S.gacc[S.np + a]);
+        if (d_charge) d_charge[a] = unfix_d(S.gacc[2 * S.np + a]) * sqrt_f;
+    }
+    if (a < S.tp.nt && d_tk) d_tk[S.tor_orig[a]] = unfix_d(S.gacc[3 * S.np + a]);
+}
+
+// dx[r] = w[r] dU_r/dx = -w[r] F_r, from the fixed-point forces
+__global__ void __launch_bounds__(256) k_weighted_dx(const Dev *__restrict__ Sp, const double *w, float *dx)
+{
+    const Dev &S = *Sp;
+    const int r = blockIdx.y;
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < S.n) {
+        const double wr = w[r];
+        for (int d = 0; d < 3; ++d)
+            dx[((size_t)r * 3 + d) * S.n + a] = (float)(-wr * unfix_d(S.F[((size_t)r * 3 + d) * S.np + a]));
+    }
+}
+
+// energies and forces of every replica out of the fixed-point accumulators
+__global__ void __launch_bounds__(256) k_unfix_out(const Dev *__restrict__ Sp, double *energy, float *forces)
+{
+    const Dev &S = *Sp;
+    const int r = blockIdx.y;
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a == 0 && energy) energy[r] = unfix_d(S.E[r]);
+    if (a < S.n && forces) {
+        for (int d = 0; d < 3; ++d)
+            forces[((size_t)r * 3 + d) * S.n + a] = (float)unfix_d(S.F[((size_t)r * 3 + d) * S.np + a]);
+    }
+}
+
 // ================================================================== persistent path
 // Barrier among the G workgroups of one replica: every thread waits for its own global
 // stores to complete, then one thread adds to the replica's counter (device-scope relaxed

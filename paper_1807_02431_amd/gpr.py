@@ -106,6 +106,10 @@ SIGNATURES = {
     "gpr_fv_plan": (C.c_int32, [C.c_uint64, C.c_int64, C.c_int32, C.POINTER(C.c_uint8), _PI]),
     "gpr_rhat": (C.c_int32, [C.c_int32, C.c_int32, C.c_int64, _PD, _PD, _PD]),
     "gpr_exit_vote": (C.c_int32, [C.c_int32, _P64, C.c_int64, _P64, C.POINTER(C.c_int32), _P64]),
+    "gpr_set_params": (C.c_int32, [_VP, _PD, _PD, _PD, _PD]),
+    "gpr_energy_forces_dev": (C.c_int32, [_VP, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gpr_energy_backward_dev": (C.c_int32, [_VP, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                            C.c_void_p]),
 }
 
 _lib = None
@@ -118,6 +122,13 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError("libgpr_hip.so is not built (run paper_1807_02431_amd/build.py); "
                               "the GPU library has no fallback path")
+        # torch ships its own HIP runtime under the same soname as the system one; whichever is
+        # loaded first serves the whole process, and torch fails to initialise on another
+        # release's.  Load torch's first so that torch and this library share it.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(L, name)
@@ -158,6 +169,7 @@ class System:
         keep = []
         n = int(spec["n_atoms"])
         self.n, self.R = n, int(spec["n_replicas"])
+        self.nt = len(spec["torsions"]) if spec.get("torsions") is not None else 0
         self.nobs = len(spec.get("obs", []))
         d = _Desc()
         d.kind, d.n_atoms, d.n_replicas = int(spec["kind"]), n, self.R
@@ -282,6 +294,23 @@ class System:
         q = _d(q).reshape(3, self.n)
         vv = None if v is None else _d(v).reshape(3, self.n)
         self._c(lib().gpr_set_state(self._h, r, _pd(q), _pd(vv)))
+
+    # -------------------------------------------------------------- differentiation
+    def set_params(self, epsilon=None, sigma=None, charge=None, torsion_k=None):
+        arrs = [None if a is None else _d(a) for a in (epsilon, sigma, charge, torsion_k)]
+        self._c(lib().gpr_set_params(self._h, *[_pd(a) if a is not None else None for a in arrs]))
+
+    def energy_forces_dev(self, x_ptr, energy_ptr, forces_ptr):
+        """Device pointers (ints): x float [R][3][n] in, energy double [R] and forces float
+        [R][3][n] out (0 for none)."""
+        self._c(lib().gpr_energy_forces_dev(self._h, C.c_void_p(x_ptr), C.c_void_p(energy_ptr or None),
+                                            C.c_void_p(forces_ptr or None)))
+
+    def energy_backward_dev(self, w_ptr, dx_ptr, d_eps_ptr, d_sigma_ptr, d_charge_ptr, d_tk_ptr):
+        """Device pointers (ints, 0 for none): weights double [R] in; dx float [R][3][n] and the
+        parameter gradients (double) out."""
+        self._c(lib().gpr_energy_backward_dev(self._h, C.c_void_p(w_ptr), *[C.c_void_p(p or None) for p in
+                                              (dx_ptr, d_eps_ptr, d_sigma_ptr, d_charge_ptr, d_tk_ptr)]))
 
     def simulated_time(self):
         return lib().gpr_simulated_time(self._h)
