@@ -98,6 +98,7 @@ def lib():
         L.gro_energy_forces.argtypes = [vp, C.c_int32, C.c_int32, _PD, _PD]
         L.gro_decorrelate.argtypes = [vp, C.c_int64, C.c_int64, C.POINTER(_Event)]
         L.gro_dephase.argtypes = [vp, C.c_int64, C.POINTER(_Dephase)]
+        L.gro_dephase_fixed.argtypes = [vp, C.c_int64, C.c_int64, C.POINTER(_Dephase)]
         L.gro_parallel_step.argtypes = [vp, C.c_int64, C.POINTER(_Exit)]
         L.gro_advance.argtypes = [vp, C.c_int64, C.POINTER(C.c_int64)]
         L.gro_step_replicas.argtypes = [vp, C.c_int64, C.c_int32, C.c_int32]
@@ -321,6 +322,12 @@ class System:
         rc = _check(lib().gro_dephase(self._h, int(max_steps), C.byref(o)), "dephase")
         return rc, dict(outcome=o.outcome, to_state=o.to_state, t_steps=o.t_steps, n_branch=o.n_branch,
                         n_samples=o.n_samples, rhat=list(o.rhat)[: self.nobs])
+
+    def dephase_fixed(self, t_phase, max_steps=1 << 62):
+        """Original ParRep dephasing (Sec. 2.4.3): every replica stays t_phase in Omega."""
+        o = _Dephase()
+        rc = _check(lib().gro_dephase_fixed(self._h, int(t_phase), int(max_steps), C.byref(o)), "dephase_fixed")
+        return rc, dict(outcome=o.outcome, to_state=o.to_state, t_steps=o.t_steps, n_branch=o.n_branch)
 
     def parallel_step(self, max_checks=1 << 62):
         o = _Exit()

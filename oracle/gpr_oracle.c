@@ -21,7 +21,7 @@
 #define STREAM_INIT 1
 #define STREAM_BRANCH 2
 
-enum { PH_IDLE = 0, PH_DECORR = 1, PH_DEPHASE = 2, PH_CONVERGED = 3, PH_PARALLEL = 4 };
+enum { PH_IDLE = 0, PH_DECORR = 1, PH_DEPHASE = 2, PH_CONVERGED = 3, PH_PARALLEL = 4, PH_DEPHASE_FIXED = 5 };
 
 struct gro_sys {
     int kind, n, R;
@@ -56,6 +56,12 @@ struct gro_sys {
     /* convergence step, resumable */
     int64_t dp_t, nsamp, n_branch;
     double *S1, *S2;              /* [R][nobs] */
+    /* original ParRep dephasing, resumable */
+    double *snap;                 /* [3][3][n]: q, v, F of the reference walker when it began */
+    double snapU;
+    int64_t *resid;               /* [R] steps in Omega since the replica's last (re)start */
+    int *done;                    /* [R] the replica has its sample */
+    double *samp, *sampU;         /* [R][3][3][n] samples (q, v, F) and their energies [R] */
     double shift[GRO_NMAXOBS];
     /* parallel step, resumable */
     int64_t par_M;
@@ -580,6 +586,7 @@ void gro_destroy(gro_sys *S)
     free(S->p14); free(S->skip); free(S->st_group);
     for (int j = 0; j < GRO_NMAXOBS; j++) { free(S->obs_ga[j]); free(S->obs_gb[j]); }
     free(S->q); free(S->v); free(S->F); free(S->U); free(S->S1); free(S->S2);
+    free(S->snap); free(S->resid); free(S->done); free(S->samp); free(S->sampU);
     free(S);
 }
 
@@ -685,7 +692,13 @@ int gro_create(const gro_spec *d, gro_sys **out)
     S->U = (double *)calloc(R, sizeof(double));
     S->S1 = (double *)calloc((size_t)R * GRO_NMAXOBS, sizeof(double));
     S->S2 = (double *)calloc((size_t)R * GRO_NMAXOBS, sizeof(double));
-    if (!S->q || !S->v || !S->F || !S->U || !S->S1 || !S->S2) { gro_destroy(S); return GRO_ENOMEM; }
+    S->snap = (double *)calloc((size_t)9 * n, sizeof(double));
+    S->resid = (int64_t *)calloc((size_t)R, sizeof(int64_t));
+    S->done = (int *)calloc((size_t)R, sizeof(int));
+    S->samp = (double *)calloc((size_t)R * 9 * n, sizeof(double));
+    S->sampU = (double *)calloc((size_t)R, sizeof(double));
+    if (!S->q || !S->v || !S->F || !S->U || !S->S1 || !S->S2 || !S->snap || !S->resid || !S->done || !S->samp ||
+        !S->sampU) { gro_destroy(S); return GRO_ENOMEM; }
 
     /* replica 0 from the descriptor; velocities drawn from Maxwell-Boltzmann if absent */
     memcpy(S->q, d->pos, sizeof(double) * 3 * n);
@@ -1011,6 +1024,86 @@ int gro_dephase(gro_sys *S, int64_t max_steps, gro_dephase_result *o)
     }
     free(ex); free(donor);
     return rc;
+}
+
+/* ------------------------------------------------------------------ original ParRep dephasing
+ * The dephasing of the original ParRep algorithm (Sec. 2.4.3), which Gen.ParRep replaces by
+ * the Fleming-Viot process: every replica starts from the reference walker's configuration
+ * and is propagated within Omega; its end point is kept as a sample of the QSD once it has
+ * stayed in Omega for t_phase.  Readings: the reference walker is one of the R samples; exits
+ * are tested every t_check_dephase steps; a replica found outside Omega at a check restarts
+ * from the configuration the reference walker had when the dephasing began (its noise goes
+ * on with the global step counter); a replica that has stayed t_phase keeps the state it had
+ * at that check as its sample (it goes on moving with the others, and what it does then is
+ * discarded); when every replica has its sample, all are set to their samples.  The
+ * dephasing time is not added to the simulation clock (the samples are prepared in parallel
+ * and their time is discarded). */
+static void save_replica(const gro_sys *S, int r, double *dst, double *dstU)
+{
+    const size_t b = sizeof(double) * 3 * (size_t)S->n;
+    memcpy(dst, Q(S, r), b);
+    memcpy(dst + 3 * S->n, Vv(S, r), b);
+    memcpy(dst + 6 * S->n, Ff(S, r), b);
+    *dstU = S->U[r];
+}
+
+static void load_replica(gro_sys *S, int r, const double *src, double U)
+{
+    const size_t b = sizeof(double) * 3 * (size_t)S->n;
+    memcpy(Q(S, r), src, b);
+    memcpy(Vv(S, r), src + 3 * S->n, b);
+    memcpy(Ff(S, r), src + 6 * S->n, b);
+    S->U[r] = U;
+}
+
+int gro_dephase_fixed(gro_sys *S, int64_t t_phase, int64_t max_steps, gro_dephase_result *o)
+{
+    const size_t per = (size_t)9 * S->n;      /* q, v, F of one replica */
+    if (S->phase != PH_DEPHASE_FIXED) {
+        if (S->omega == -1) { set_err("reference walker is in no state"); return GRO_EPHASE; }
+        if (t_phase < 0) { set_err("t_phase < 0"); return GRO_EINVAL; }
+        save_replica(S, 0, S->snap, &S->snapU);
+        for (int r = 1; r < S->R; r++) copy_replica(S, r, 0);
+        for (int r = 0; r < S->R; r++) { S->resid[r] = 0; S->done[r] = 0; }
+        S->dp_t = 0;
+        S->n_branch = 0;
+        S->phase = PH_DEPHASE_FIXED;
+    }
+    int64_t taken = 0;
+    while (taken < max_steps) {
+        int e = step_all(S, S->R);
+        if (e) return e;
+        S->dp_t += 1;
+        taken += 1;
+        if (S->dp_t % S->tcd != 0) continue;
+        int all = 1;
+        for (int r = 0; r < S->R; r++) {
+            if (S->done[r]) continue;
+            if (gro_state_of(S, Q(S, r)) != S->omega) {
+                load_replica(S, r, S->snap, S->snapU);
+                S->resid[r] = 0;
+                S->n_branch += 1;
+                all = 0;
+            } else {
+                S->resid[r] += S->tcd;
+                if (S->resid[r] >= t_phase) {
+                    save_replica(S, r, S->samp + (size_t)r * per, &S->sampU[r]);
+                    S->done[r] = 1;
+                } else {
+                    all = 0;
+                }
+            }
+        }
+        if (all) {
+            for (int r = 0; r < S->R; r++) load_replica(S, r, S->samp + (size_t)r * per, S->sampU[r]);
+            o->outcome = 0; o->to_state = S->omega; o->t_steps = S->dp_t;
+            o->n_branch = S->n_branch; o->n_samples = 0;
+            for (int j = 0; j < GRO_NMAXOBS; j++) o->rhat[j] = 0.0;
+            S->phase = PH_CONVERGED;
+            return GRO_OK;
+        }
+    }
+    return GRO_BUDGET;
 }
 
 /* ------------------------------------------------------------------ parallel step

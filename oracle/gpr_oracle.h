@@ -105,6 +105,7 @@ int  gro_param_grad(const gro_sys *S, const double *q, double *dU_eps, double *d
 int  gro_energy_forces(const gro_sys *S, int32_t r0, int32_t nr, double *E, double *F);
 int  gro_decorrelate(gro_sys *S, int64_t t_corr, int64_t max_steps, gro_event *ev);
 int  gro_dephase(gro_sys *S, int64_t max_steps, gro_dephase_result *o);
+int  gro_dephase_fixed(gro_sys *S, int64_t t_phase, int64_t max_steps, gro_dephase_result *o);
 int  gro_parallel_step(gro_sys *S, int64_t max_checks, gro_exit_result *o);
 int  gro_advance(gro_sys *S, int64_t nsteps, int64_t *first_exit_check);
 int  gro_step_replicas(gro_sys *S, int64_t nsteps, int32_t r_lo, int32_t r_hi);

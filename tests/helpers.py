@@ -60,6 +60,31 @@ def gen_parrep_exits(sys, n_exits, t_corr):
     return out
 
 
+def original_parrep_exits(sys, n_exits, t_corr, t_phase):
+    """The original ParRep loop (Sec. 2.4.3): decorrelation with a fixed residence time
+    t_corr, dephasing with a fixed time t_phase, then the parallel step; one record per exit
+    as in gen_parrep_exits."""
+    out = []
+    last = sys.simulated_steps()
+    omega = sys.current_state()
+    while len(out) < n_exits:
+        rc, ev = sys.decorrelate(t_corr)
+        assert rc == 0
+        if ev["kind"] == 1:
+            now = sys.simulated_steps()
+            out.append((now - last, ev["from_state"], ev["to_state"], "transient", 0))
+            last, omega = now, ev["to_state"]
+            continue
+        rc, o = sys.dephase_fixed(t_phase)
+        assert rc == 0 and o["outcome"] == 0
+        rc, e = sys.parallel_step()
+        assert rc == 0
+        now = sys.simulated_steps()
+        out.append((now - last, omega, e["to_state"], "parallel", e["tau_steps"]))
+        last, omega = now, e["to_state"]
+    return out
+
+
 def direct_exits(sys, n_exits):
     """Brute-force direct simulation of the reference walker with the same exit-check
     period: decorrelation with an unbounded residence time never accepts a state, so
