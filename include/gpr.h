@@ -278,6 +278,17 @@ gpr_status gpr_decorrelate(gpr_system *sys, int64_t t_corr_steps, int64_t max_st
  * GPR_BUDGET after max_steps steps in this call (the dephasing resumes on the next call). */
 gpr_status gpr_dephase(gpr_system *sys, int64_t max_steps, gpr_dephase_out *o);
 
+/* Dephasing of the original ParRep algorithm (Sec. 2.4.3), the step that Gen.ParRep replaces by
+ * the Fleming-Viot process: all R replicas start from the reference walker's configuration and
+ * a replica's sample is the state it has at the first check (every t_check_dephase steps) at
+ * which it has stayed in Omega for t_phase steps since its last (re)start; a replica found
+ * outside Omega at a check restarts from that start configuration.  When every replica has its
+ * sample, all are set to their samples and gpr_parallel_step may follow.  The dephasing time
+ * is not added to t_sim.  o->t_steps: steps taken, o->n_branch: restarts.  Resumable
+ * (GPR_BUDGET after max_steps); EPHASE if the reference walker is in no state, EINVAL for
+ * t_phase < 0. */
+gpr_status gpr_dephase_fixed(gpr_system *sys, int64_t t_phase, int64_t max_steps, gpr_dephase_out *o);
+
 /* Parallel dynamics step, Sec. 2.4.2: after a converged dephasing, all R replicas step
  * t_check_parallel steps between checks; at the first check M where some replica left Omega,
  * k = 1 + the smallest such index, tau = (R (M-1) + k) t_check_parallel (Eq. 5),

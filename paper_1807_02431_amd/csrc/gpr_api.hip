@@ -22,7 +22,7 @@ using namespace gpr;
 namespace {
 
 constexpr double COULOMB_F = 138.935458;
-enum { PH_IDLE = 0, PH_DECORR = 1, PH_DEPHASE = 2, PH_CONVERGED = 3, PH_PARALLEL = 4 };
+enum { PH_IDLE = 0, PH_DECORR = 1, PH_DEPHASE = 2, PH_CONVERGED = 3, PH_PARALLEL = 4, PH_DEPHASE_FIXED = 5 };
 
 thread_local std::string g_thread_err;
 
@@ -55,6 +55,11 @@ struct gpr_system {
     long long dc_resid = 0, dc_steps = 0;
     long long dp_t = 0, nsamp = 0, n_branch = 0;
     long long par_M = 0;
+    // original ParRep dephasing: start configuration, samples, per-replica progress
+    float *snap_x = nullptr, *snap_v = nullptr, *samp_x = nullptr, *samp_v = nullptr;
+    long long *snap_F = nullptr, *samp_F = nullptr;
+    std::vector<long long> resid;
+    std::vector<int> done;
     // scratch
     Status *st_dev = nullptr, *st_host = nullptr;
     double *obs_out = nullptr;
@@ -1204,6 +1209,99 @@ extern "C" gpr_status gpr_dephase(gpr_system *S, int64_t max_steps, gpr_dephase_
             S->phase = PH_CONVERGED;
             return GPR_OK;
         }
+    }
+    return GPR_BUDGET;
+}
+
+// copies the (x, v, F) of one replica between the system and a replica-sized buffer set
+static gpr_status move_replica(gpr_system *S, float *dx, float *dv, long long *dF, const float *sx, const float *sv,
+                               const long long *sF)
+{
+    const size_t m = (size_t)3 * S->np;
+    HIPCHK(S, hipMemcpyAsync(dx, sx, sizeof(float) * m, hipMemcpyDeviceToDevice, S->stream));
+    HIPCHK(S, hipMemcpyAsync(dv, sv, sizeof(float) * m, hipMemcpyDeviceToDevice, S->stream));
+    HIPCHK(S, hipMemcpyAsync(dF, sF, sizeof(long long) * m, hipMemcpyDeviceToDevice, S->stream));
+    return GPR_OK;
+}
+
+extern "C" gpr_status gpr_dephase_fixed(gpr_system *S, int64_t t_phase, int64_t max_steps, gpr_dephase_out *o)
+{
+    if (!S || !o) return fail(S, GPR_EINVAL, "NULL argument");
+    const int R = S->R;
+    const size_t m = (size_t)3 * S->np;
+    Dev &d = S->d;
+    gpr_status rc;
+    if (S->phase != PH_DEPHASE_FIXED) {
+        if (S->omega == -1) return fail(S, GPR_EPHASE, "reference walker is in no state");
+        if (t_phase < 0) return fail(S, GPR_EINVAL, "t_phase < 0");
+        if (!S->snap_x) {
+            HIPCHK(S, dalloc(S, &S->snap_x, m)); HIPCHK(S, dalloc(S, &S->snap_v, m)); HIPCHK(S, dalloc(S, &S->snap_F, m));
+            HIPCHK(S, dalloc(S, &S->samp_x, m * R)); HIPCHK(S, dalloc(S, &S->samp_v, m * R));
+            HIPCHK(S, dalloc(S, &S->samp_F, m * R));
+        }
+        rc = move_replica(S, S->snap_x, S->snap_v, S->snap_F, d.x, d.v, d.F);
+        if (rc) return rc;
+        rc = broadcast_reference(S);
+        if (rc) return rc;
+        S->resid.assign(R, 0);
+        S->done.assign(R, 0);
+        S->dp_t = 0;
+        S->n_branch = 0;
+        S->phase = PH_DEPHASE_FIXED;
+    }
+    const int one = 1;
+    std::vector<int> st(R);
+    long long taken = 0;
+    while (taken < max_steps) {
+        const long long k = std::min<long long>(S->tcd - S->dp_t % S->tcd, max_steps - taken);
+        const bool at_check = (S->dp_t + k) % S->tcd == 0;
+        rc = run_steps(S, R, k, S->dp_t, false, at_check);
+        if (rc) return rc;
+        S->dp_t += k;
+        taken += k;
+        if (!at_check) break;
+        HIPCHK(S, hipMemcpyAsync(st.data(), d.state, sizeof(int) * R, hipMemcpyDeviceToHost, S->stream));
+        int err[4];
+        HIPCHK(S, hipMemcpyAsync(err, d.err, sizeof err, hipMemcpyDeviceToHost, S->stream));
+        HIPCHK(S, hipStreamSynchronize(S->stream));
+        if (err[ERR_UNSTABLE]) return fail(S, GPR_EUNSTABLE, "non-finite or overflowing state");
+        if (err[ERR_BARRIER]) return fail(S, GPR_EDEVICE, "persistent kernel barrier timed out");
+        if (err[ERR_LIST]) return fail(S, GPR_EDEVICE, "pair-list capacity exceeded");
+        bool all = true;
+        for (int r = 0; r < R; ++r) {
+            if (S->done[r]) continue;
+            const size_t b = (size_t)r * m;
+            if (st[r] != S->omega) {
+                rc = move_replica(S, d.x + b, d.v + b, d.F + b, S->snap_x, S->snap_v, S->snap_F);
+                if (rc) return rc;
+                HIPCHK(S, hipMemcpyAsync(d.need_build + r, &one, sizeof(int), hipMemcpyHostToDevice, S->stream));
+                S->resid[r] = 0;
+                S->n_branch += 1;
+                all = false;
+            } else if ((S->resid[r] += S->tcd) >= t_phase) {
+                rc = move_replica(S, S->samp_x + b, S->samp_v + b, S->samp_F + b, d.x + b, d.v + b, d.F + b);
+                if (rc) return rc;
+                S->done[r] = 1;
+            } else {
+                all = false;
+            }
+        }
+        if (all) {
+            for (int r = 0; r < R; ++r) {
+                const size_t b = (size_t)r * m;
+                rc = move_replica(S, d.x + b, d.v + b, d.F + b, S->samp_x + b, S->samp_v + b, S->samp_F + b);
+                if (rc) return rc;
+            }
+            std::vector<int> ones(R, 1);
+            HIPCHK(S, hipMemcpyAsync(d.need_build, ones.data(), sizeof(int) * R, hipMemcpyHostToDevice, S->stream));
+            HIPCHK(S, hipStreamSynchronize(S->stream));
+            o->outcome = GPR_DEPHASE_CONVERGED; o->to_state = S->omega; o->t_steps = S->dp_t;
+            o->n_branch = S->n_branch; o->n_samples = 0;
+            for (int j = 0; j < GPR_MAX_OBS; ++j) o->rhat[j] = 0.0;
+            S->phase = PH_CONVERGED;
+            return GPR_OK;
+        }
+        HIPCHK(S, hipStreamSynchronize(S->stream));
     }
     return GPR_BUDGET;
 }

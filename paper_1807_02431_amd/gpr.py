@@ -106,6 +106,7 @@ SIGNATURES = {
     "gpr_fv_plan": (C.c_int32, [C.c_uint64, C.c_int64, C.c_int32, C.POINTER(C.c_uint8), _PI]),
     "gpr_rhat": (C.c_int32, [C.c_int32, C.c_int32, C.c_int64, _PD, _PD, _PD]),
     "gpr_exit_vote": (C.c_int32, [C.c_int32, _P64, C.c_int64, _P64, C.POINTER(C.c_int32), _P64]),
+    "gpr_dephase_fixed": (C.c_int32, [_VP, C.c_int64, C.c_int64, C.POINTER(_Dephase)]),
     "gpr_set_params": (C.c_int32, [_VP, _PD, _PD, _PD, _PD]),
     "gpr_energy_forces_dev": (C.c_int32, [_VP, C.c_void_p, C.c_void_p, C.c_void_p]),
     "gpr_energy_backward_dev": (C.c_int32, [_VP, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -350,6 +351,11 @@ class System:
         rc = self._c(lib().gpr_dephase(self._h, int(max_steps), C.byref(o)))
         return rc, dict(outcome=o.outcome, to_state=o.to_state, t_steps=o.t_steps, n_branch=o.n_branch,
                         n_samples=o.n_samples, rhat=list(o.rhat)[: self.nobs])
+
+    def dephase_fixed(self, t_phase, max_steps=1 << 62):
+        o = _Dephase()
+        rc = self._c(lib().gpr_dephase_fixed(self._h, int(t_phase), int(max_steps), C.byref(o)))
+        return rc, dict(outcome=o.outcome, to_state=o.to_state, t_steps=o.t_steps, n_branch=o.n_branch)
 
     def parallel_step(self, max_checks=1 << 62):
         o = _Exit()
