@@ -219,6 +219,15 @@ gpr_status gpr_set_path(gpr_system *sys, int32_t path);
  * fit on the device at once.  Results do not depend on the shape. */
 gpr_status gpr_set_launch(gpr_system *sys, int32_t block_threads, int32_t groups_per_replica);
 
+/* Autotuner of the persistent path's launch shape: every (threads per workgroup in {256, 512,
+ * 768, 1024}, workgroups per replica in {1, 2, 4, 8}) that fits the device is timed over nsteps
+ * steps from the same saved state, and the fastest becomes the launch shape (written to
+ * *block_threads and *groups when not NULL).  The state is restored afterwards (every pair list
+ * is rebuilt at the next step), so later results are those of a run without the call.  Device
+ * scratch for one copy of the replicas' state is allocated and freed within the call.  EINVAL
+ * if nsteps < 1 or the persistent path does not fit. */
+gpr_status gpr_autotune(gpr_system *sys, int32_t nsteps, int32_t *block_threads, int32_t *groups);
+
 /* ---------------------------------------------------------------- force field (Sec. 3.2) */
 /* Energy and forces of replicas [r0, r0+nr) at their current positions.
  * energy: [nr] or NULL; forces: [nr][3][n_atoms] (SoA per replica) or NULL; host buffers.

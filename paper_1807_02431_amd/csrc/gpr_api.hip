@@ -895,6 +895,114 @@ extern "C" gpr_status gpr_set_launch(gpr_system *S, int32_t block_threads, int32
     return GPR_OK;
 }
 
+// Launch-shape autotuner of the persistent path: every (threads per workgroup, workgroups per
+// replica) shape that fits is timed over nsteps steps (after a short warm-up), starting each
+// time from the same saved state; the fastest is kept.  The saved state (positions,
+// velocities, forces, list-reference positions and ages, step counter) is put back at the end
+// with every pair list marked for a rebuild, so the run continues exactly as without the call
+// (results do not depend on the shape or on when lists are rebuilt).
+extern "C" gpr_status gpr_autotune(gpr_system *S, int32_t nsteps, int32_t *block_threads, int32_t *groups)
+{
+    if (!S) return fail(nullptr, GPR_EINVAL, "NULL system");
+    if (nsteps < 1) return fail(S, GPR_EINVAL, "nsteps < 1");
+    if (!S->persist_ok) return fail(S, GPR_EINVAL, "system too large for the persistent path");
+    const int R = S->R;
+    const size_t m = (size_t)R * 3 * S->np;
+    Dev &d = S->d;
+    // saved state, in scratch freed when the call returns
+    struct Scratch {
+        std::vector<void *> p;
+        ~Scratch() { for (void *q : p) (void)hipFree(q); }
+        hipError_t get(void **out, size_t bytes)
+        {
+            const hipError_t e = hipMalloc(out, bytes);
+            if (e == hipSuccess) p.push_back(*out);
+            return e;
+        }
+    } scratch;
+    float *sx = nullptr, *sv = nullptr, *sxb = nullptr;
+    long long *sF = nullptr, *slb = nullptr;
+    HIPCHK(S, scratch.get((void **)&sx, sizeof(float) * m));
+    HIPCHK(S, scratch.get((void **)&sv, sizeof(float) * m));
+    HIPCHK(S, scratch.get((void **)&sxb, sizeof(float) * m));
+    HIPCHK(S, scratch.get((void **)&sF, sizeof(long long) * m));
+    HIPCHK(S, scratch.get((void **)&slb, sizeof(long long) * 2 * R));
+    auto copy_all = [&](bool save) -> hipError_t {
+        const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+        hipError_t e = hipMemcpyAsync(save ? sx : d.x, save ? d.x : sx, sizeof(float) * m, k, S->stream);
+        if (!e) e = hipMemcpyAsync(save ? sv : d.v, save ? d.v : sv, sizeof(float) * m, k, S->stream);
+        if (!e) e = hipMemcpyAsync(save ? sxb : d.xb, save ? d.xb : sxb, sizeof(float) * m, k, S->stream);
+        if (!e) e = hipMemcpyAsync(save ? sF : d.F, save ? d.F : sF, sizeof(long long) * m, k, S->stream);
+        if (!e) e = hipMemcpyAsync(save ? slb : d.last_build, save ? d.last_build : slb, sizeof(long long) * 2 * R, k, S->stream);
+        if (!e && !save) {
+            std::vector<int> ones(R, 1);
+            e = hipMemcpyAsync(d.need_build, ones.data(), sizeof(int) * R, hipMemcpyHostToDevice, S->stream);
+            if (!e) e = hipStreamSynchronize(S->stream);
+        }
+        return e;
+    };
+    HIPCHK(S, copy_all(true));
+    const long long s_saved = S->s;
+    const int path_saved = S->path, bt_saved = S->bt_persist, g_saved = S->groups;
+    const Split sp_saved = S->split;
+    int dev = 0, cus = 0;
+    HIPCHK(S, hipGetDevice(&dev));
+    HIPCHK(S, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    hipEvent_t e0, e1;
+    HIPCHK(S, hipEventCreate(&e0));
+    HIPCHK(S, hipEventCreate(&e1));
+    float best = -1.f;
+    int best_bt = bt_saved, best_g = g_saved;
+    gpr_status rc = GPR_OK;
+    S->path = GPR_PATH_PERSISTENT;
+    for (int G = 1; G <= 8 && rc == GPR_OK; G *= 2) {
+        const Split sp = make_split(S->work, S->n, S->np, G);
+        const size_t lds = persist_lds(S->n, S->np, sp);
+        if ((int)lds > S->maxlds_persist) continue;
+        for (int bt = 256; bt <= 1024 && rc == GPR_OK; bt += 256) {
+            if (G > 1) {
+                int per_cu = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_persist, bt, lds) != hipSuccess ||
+                    (long)R * G > (long)per_cu * cus)
+                    continue;
+            }
+            S->bt_persist = bt; S->groups = G; S->split = sp;
+            hipError_t he = copy_all(false);
+            if (he) { rc = fail(S, GPR_EDEVICE, std::string("autotune restore: ") + hipGetErrorString(he)); break; }
+            S->s = s_saved;
+            rc = run_steps(S, R, std::min(20, nsteps), 0, false, false);
+            if (rc) break;
+            HIPCHK(S, hipEventRecord(e0, S->stream));
+            rc = run_steps(S, R, nsteps, 0, false, false);
+            if (rc) break;
+            HIPCHK(S, hipEventRecord(e1, S->stream));
+            HIPCHK(S, hipEventSynchronize(e1));
+            int err[4];
+            HIPCHK(S, hipMemcpy(err, d.err, sizeof err, hipMemcpyDeviceToHost));
+            if (err[ERR_UNSTABLE] || err[ERR_BARRIER] || err[ERR_LIST]) { rc = fail(S, GPR_EDEVICE, "autotune run failed"); break; }
+            float ms = 0.f;
+            HIPCHK(S, hipEventElapsedTime(&ms, e0, e1));
+            if (best < 0.f || ms < best) { best = ms; best_bt = bt; best_g = G; }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // back to the saved state with the chosen shape
+    S->path = path_saved;
+    S->s = s_saved;
+    HIPCHK(S, copy_all(false));
+    if (rc) {
+        S->bt_persist = bt_saved; S->groups = g_saved; S->split = sp_saved;
+        return rc;
+    }
+    S->bt_persist = best_bt;
+    S->groups = best_g;
+    S->split = make_split(S->work, S->n, S->np, best_g);
+    if (block_threads) *block_threads = best_bt;
+    if (groups) *groups = best_g;
+    return GPR_OK;
+}
+
 extern "C" gpr_status gpr_profile(gpr_system *S, int32_t enable)
 {
     if (!S) return fail(nullptr, GPR_EINVAL, "NULL system");

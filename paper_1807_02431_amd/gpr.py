@@ -107,6 +107,7 @@ SIGNATURES = {
     "gpr_rhat": (C.c_int32, [C.c_int32, C.c_int32, C.c_int64, _PD, _PD, _PD]),
     "gpr_exit_vote": (C.c_int32, [C.c_int32, _P64, C.c_int64, _P64, C.POINTER(C.c_int32), _P64]),
     "gpr_dephase_fixed": (C.c_int32, [_VP, C.c_int64, C.c_int64, C.POINTER(_Dephase)]),
+    "gpr_autotune": (C.c_int32, [_VP, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "gpr_set_params": (C.c_int32, [_VP, _PD, _PD, _PD, _PD]),
     "gpr_energy_forces_dev": (C.c_int32, [_VP, C.c_void_p, C.c_void_p, C.c_void_p]),
     "gpr_energy_backward_dev": (C.c_int32, [_VP, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -264,6 +265,12 @@ class System:
 
     def set_path(self, path):
         self._c(lib().gpr_set_path(self._h, int(path)))
+
+    def autotune(self, nsteps=200):
+        """Times the persistent path's launch shapes and keeps the fastest; returns it."""
+        bt, g = C.c_int32(), C.c_int32()
+        self._c(lib().gpr_autotune(self._h, int(nsteps), C.byref(bt), C.byref(g)))
+        return bt.value, g.value
 
     def set_launch(self, block_threads=0, groups_per_replica=0):
         self._c(lib().gpr_set_launch(self._h, int(block_threads), int(groups_per_replica)))
