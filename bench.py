@@ -152,6 +152,36 @@ def differentiation_bench(spec, iters):
                 "backward = dU/dx and dU/d(eps, sigma, q, torsion k) summed over replicas")
 
 
+def batching_bench(steps):
+    """The uneven mix (22 / 300 / 1,200 / 2,432 atoms x 192 replicas) advanced in shared
+    persistent launches, against the same systems advanced one after the other."""
+    import torch
+    import gpr_synth as G
+    import paper_1807_02431_amd as gpr
+    specs = G.uneven_batch(192)
+    stream = torch.cuda.current_stream()
+    batch = [gpr.System(s, path=gpr.PATH_PERSISTENT, stream=stream) for s in specs]
+    solo = [gpr.System(s, path=gpr.PATH_PERSISTENT, stream=stream) for s in specs]
+    gpr.batch_advance(batch, 100)
+    for x in solo:
+        x.advance(100)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gpr.batch_advance(batch, steps)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for x in solo:
+        x.advance(steps)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    reps = sum(s["n_replicas"] for s in specs)
+    atoms = sum(s["n_replicas"] * s["n_atoms"] for s in specs)
+    return dict(systems="22, 300, 1200, 2432 atoms x 192 replicas each", replicas=reps, steps=steps,
+                replica_steps_per_s=reps * steps / tb, atom_steps_per_s=atoms * steps / tb,
+                separate_replica_steps_per_s=reps * steps / ts, speedup_vs_separate=ts / tb)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +190,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the uneven multi-system batching measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 256 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -218,6 +249,11 @@ def main():
         print("# differentiation: forward + backward", file=sys.stderr, flush=True)
         diff = differentiation_bench(spec, 50)
 
+    batching = None
+    if not args.no_batch:
+        print("# uneven multi-system batching", file=sys.stderr, flush=True)
+        batching = batching_bench(1000)
+
     cpu = None if args.no_cpu else cpu_baseline(spec)
 
     steps_per_launch = args.steps / max(klaunch, 1)
@@ -250,6 +286,7 @@ def main():
                      "in_cutoff_pairs_per_replica": pairs},
         "cpu_baseline": cpu,
         "differentiation": diff,
+        "batching": batching,
     }
     print(json.dumps(out), flush=True)
 

@@ -318,7 +318,7 @@ def receptor_ligand(seed: int = 3, n_replicas: int = 64, n_receptor: int = 2400,
 def config(name: str, **kw):
     """The named workloads: 'toy' (2D double well, R = 8), 'chain22' (22 atoms, R = 256),
     'rl2432' (2,400 + 32 atoms, R = 64), 'rl300' (a 268 + 32-atom receptor-ligand system of
-    the uneven-batching mix)."""
+    the uneven-batching mix), 'rl1200' (1,168 + 32 atoms, also of that mix)."""
     if name == "toy":
         return toy2d(**kw)
     if name == "chain22":
@@ -329,4 +329,14 @@ def config(name: str, **kw):
         kw.setdefault("n_receptor", 268)
         kw.setdefault("radius", 2.2)
         return receptor_ligand(**kw)
+    if name == "rl1200":
+        kw.setdefault("n_receptor", 1168)
+        kw.setdefault("radius", 3.2)
+        return receptor_ligand(**kw)
     raise KeyError(name)
+
+
+def uneven_batch(n_replicas: int = 192):
+    """The uneven-batching mix: systems of 22, 300, 1,200 and 2,432 atoms (the chain and three
+    receptor-ligand systems, each with its own state function), n_replicas each."""
+    return [config(name, n_replicas=n_replicas) for name in ("chain22", "rl300", "rl1200", "rl2432")]

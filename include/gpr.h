@@ -213,10 +213,11 @@ gpr_status gpr_set_stream(gpr_system *sys, void *hip_stream);
 gpr_status gpr_set_path(gpr_system *sys, int32_t path);
 /* Launch shape of the persistent path: threads per workgroup (multiple of 64, <= 1024) and
  * workgroups per replica (1, 2, 4 or 8; a replica's atoms are split between its workgroups,
- * which exchange positions every step).  0 keeps the current value.  EINVAL, with nothing
- * changed, if one workgroup's share of a replica does not fit in LDS (large systems need
- * several workgroups per replica) or if the replicas times the workgroups per replica do not
- * fit on the device at once.  Results do not depend on the shape. */
+ * which exchange positions every step).  0 keeps the current value.  When the replicas times
+ * the workgroups per replica exceed what the device holds at once, sets of workgroups take the
+ * replicas in turn.  EINVAL, with nothing changed, if one workgroup's share of a replica does
+ * not fit in LDS (large systems need several workgroups per replica) or a workgroup of that
+ * size cannot run.  Results do not depend on the shape. */
 gpr_status gpr_set_launch(gpr_system *sys, int32_t block_threads, int32_t groups_per_replica);
 
 /* Autotuner of the persistent path's launch shape: every (threads per workgroup in {256, 512,
@@ -328,6 +329,17 @@ gpr_status gpr_set_state(gpr_system *sys, int32_t r, const double *q, const doub
  * within this call at which state != Omega (0 if none).  The fixed-work stepping loop of
  * the measurement harness. */
 gpr_status gpr_advance(gpr_system *sys, int64_t nsteps, int64_t *first_exit_check);
+
+/* gpr_advance of several systems (1 to 8, each its own handle, all on one stream and able to
+ * use the persistent path) whose persistent steps share launches: each launch advances every
+ * system up to the next exit check of any of them (their t_check_dephase may differ), the
+ * workgroups shared out in proportion to each system's work per step; sets of workgroups take
+ * a system's replicas in turn when they do not all fit at once.  Per system the result is
+ * bit-identical to gpr_advance.  first_exit_check: NULL, or nsys pointers (each NULL or
+ * [n_replicas]).  EINVAL for a repeated handle, different streams, or more workgroups than
+ * the device holds at once. */
+gpr_status gpr_batch_advance(gpr_system *const *systems, int32_t nsys, int64_t nsteps,
+                             int64_t *const *first_exit_check);
 
 /* Timing of the dominant stepping kernel (the persistent kernel on the persistent path,
  * the pair-force kernel on the plain path) with HIP events recorded on the system's

@@ -297,6 +297,64 @@ static gpr_status launch_forces(gpr_system *S, int r_off, int nrep, long long s,
 
 // advances replicas [0, nrep) by nsteps from local step counter t0; sample: accumulate the
 // observables of workers every t_gr; state_end: state ids at the end
+// Workgroup sets of one system in a persistent launch.  One workgroup per replica needs no
+// co-residency (normal launch, one workgroup per replica); G > 1 workgroups per replica
+// synchronise, so all workgroups of the launch must be resident together (cooperative launch)
+// and the replicas are shared by at most capacity / G sets (cap_blocks < 0: the whole device).
+static gpr_status persist_item(gpr_system *S, int nrep, int bt, size_t lds, int cap_blocks, PersistItem &it,
+                               int &nblocks, bool &coop)
+{
+    const int G = S->groups;
+    it = PersistItem{};
+    it.dev = S->d_dev;
+    it.sp = S->split;
+    it.nrep = nrep;
+    it.boff = 0;
+    if (G == 1 && cap_blocks < 0) {
+        it.nsets = nrep;
+        it.xcd = 0;
+        nblocks = nrep;
+        coop = false;
+        return GPR_OK;
+    }
+    if (cap_blocks < 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        HIPCHK(S, hipGetDevice(&dev));
+        HIPCHK(S, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        HIPCHK(S, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_persist, bt, lds));
+        cap_blocks = per_cu * cus;
+    }
+    int nsets = std::min(nrep, cap_blocks / G);
+    if (nsets < 1) return fail(S, GPR_EINVAL, "a replica's workgroups do not fit on the device at once");
+    it.xcd = 0;
+    if (G > 1 && nsets >= 8) {
+        nsets -= nsets % 8;
+        it.xcd = 1;
+    }
+    it.nsets = nsets;
+    nblocks = nsets * G;
+    coop = true;
+    return GPR_OK;
+}
+
+// A single item with a set per replica runs k_persist; anything else (several systems, or
+// sets that take replicas in turn) runs k_persist_batch.
+static gpr_status launch_persist(gpr_system *S, PersistBatch &pb, int nblocks, int bt, size_t lds, bool coop,
+                                 hipStream_t stream)
+{
+    const bool single = pb.nitems == 1 && pb.it[0].nsets >= pb.it[0].nrep;
+    const void *fn = single ? (const void *)k_persist : (const void *)k_persist_batch;
+    void *args_single[] = {(void *)&pb.it[0]};
+    void *args_batch[] = {(void *)&pb};
+    void **args = single ? args_single : args_batch;
+    if (!coop) {
+        HIPCHK(S, hipLaunchKernel(fn, dim3(nblocks), dim3(bt), args, lds, stream));
+    } else {
+        HIPCHK(S, hipLaunchCooperativeKernel(fn, dim3(nblocks), dim3(bt), args, (unsigned)lds, stream));
+    }
+    return GPR_OK;
+}
+
 static gpr_status run_steps(gpr_system *S, int nrep, long long nsteps, long long t0, bool sample, bool state_end)
 {
     if (nsteps <= 0) {
@@ -307,30 +365,27 @@ static gpr_status run_steps(gpr_system *S, int nrep, long long nsteps, long long
         return GPR_OK;
     }
     if (S->path == GPR_PATH_PERSISTENT) {
+        PersistBatch pb{};
+        pb.nitems = 1;
+        int nblocks = 0;
+        bool coop = false;
+        const size_t lds = persist_lds(S->n, S->np, S->split);
+        gpr_status rc = persist_item(S, nrep, S->bt_persist, lds, -1, pb.it[0], nblocks, coop);
+        if (rc) return rc;
         long long done = 0;
-        const int G = S->groups;
-        const Split sp = S->split;
-        const size_t lds = persist_lds(S->n, S->np, sp);
         while (done < nsteps) {
             const int chunk = (int)std::min<long long>(nsteps - done, 1 << 20);
             const bool last = done + chunk == nsteps;
-            long long s0 = S->s + done;
-            int steps = chunk, tstart = (int)(t0 + done), samp = sample ? 1 : 0, send = (state_end && last) ? 1 : 0;
-            int nrep_ = nrep;
-            Split sp_ = sp;
-            if (G > 1) HIPCHK(S, hipMemsetAsync(S->d.sync, 0, sizeof(int) * 64 * S->R, S->stream));
+            PersistItem &it = pb.it[0];
+            it.s0 = S->s + done;
+            it.nsteps = chunk;
+            it.t0 = (int)(t0 + done);
+            it.sample = sample ? 1 : 0;
+            it.state_end = (state_end && last) ? 1 : 0;
+            if (S->groups > 1) HIPCHK(S, hipMemsetAsync(S->d.sync, 0, sizeof(int) * 64 * S->R, S->stream));
             HIPCHK(S, prof_begin(S));
-            if (G == 1) {
-                hipLaunchKernelGGL(k_persist, dim3(nrep), dim3(S->bt_persist), lds, S->stream, S->d_dev, s0, steps,
-                                   tstart, samp, send, sp_, nrep_);
-                LAUNCHCHK(S);
-            } else {
-                // all groups of a replica must be resident together: cooperative launch
-                const Dev *dp = S->d_dev;
-                void *args[] = {(void *)&dp, &s0, &steps, &tstart, &samp, &send, &sp_, &nrep_};
-                HIPCHK(S, hipLaunchCooperativeKernel((const void *)k_persist, dim3(nrep * G), dim3(S->bt_persist), args,
-                                                     (unsigned)lds, S->stream));
-            }
+            rc = launch_persist(S, pb, nblocks, S->bt_persist, lds, coop, S->stream);
+            if (rc) return rc;
             HIPCHK(S, prof_end(S));
             done += chunk;
         }
@@ -720,6 +775,11 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
         S->maxlds_persist = maxlds - (int)fa.sharedSizeBytes;
         HIPCHK(S, hipFuncSetAttribute((const void *)k_persist, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       S->maxlds_persist));
+        hipFuncAttributes fb{};
+        HIPCHK(S, hipFuncGetAttributes(&fb, (const void *)k_persist_batch));
+        if ((int)fb.sharedSizeBytes != (int)fa.sharedSizeBytes) return fail(S, GPR_EDEVICE, "persistent kernels differ in static LDS");
+        HIPCHK(S, hipFuncSetAttribute((const void *)k_persist_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      S->maxlds_persist));
     }
     S->bt_persist = std::min(1024, std::max(64, (n * P + 63) / 64 * 64));
     {
@@ -729,29 +789,31 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
         int cus = 0;
         HIPCHK(S, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         S->max_coresident = cus;
-        auto usable = [&](int G, bool &ok) -> hipError_t {
+        // usable: the LDS fits and a workgroup can run; all_at_once: every replica's workgroups are
+        // resident together (with fewer, sets of workgroups take the replicas in turn)
+        auto usable = [&](int G, bool &ok, bool &all_at_once) -> hipError_t {
             const size_t lds = persist_lds(n, np, make_split(S->work, n, np, G));
-            ok = false;
+            ok = all_at_once = false;
             if ((int)lds > S->maxlds_persist) return hipSuccess;
-            if (G == 1) { ok = true; return hipSuccess; }
             int per_cu = 0;
             const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_persist,
                                                                               S->bt_persist, lds);
-            ok = e == hipSuccess && (long)R * G <= (long)per_cu * cus;
+            ok = e == hipSuccess && per_cu >= 1;
+            all_at_once = ok && (G == 1 || (long)R * G <= (long)per_cu * cus);
             return e;
         };
         int G = 1;
-        bool ok = false;
+        bool ok = false, all = false;
         for (; G <= 8; G *= 2) {
-            HIPCHK(S, usable(G, ok));
+            HIPCHK(S, usable(G, ok, all));
             if (ok) break;
         }
         S->persist_ok = ok ? 1 : 0;
         if (ok) {
             while (G < 8 && (n + 2 * G - 1) / (2 * G) >= 256) {
-                bool ok2 = false;
-                HIPCHK(S, usable(2 * G, ok2));
-                if (!ok2) break;
+                bool ok2 = false, all2 = false;
+                HIPCHK(S, usable(2 * G, ok2, all2));
+                if (!ok2 || !all2) break;
                 G *= 2;
             }
         } else {
@@ -878,14 +940,9 @@ extern "C" gpr_status gpr_set_launch(gpr_system *S, int32_t block_threads, int32
         const size_t lds = persist_lds(S->n, S->np, make_split(S->work, S->n, S->np, G));
         if ((int)lds > S->maxlds_persist)
             return fail(S, GPR_EINVAL, "the per-workgroup LDS of this split exceeds the device limit");
-        if (G > 1) {
-            int dev = 0, cus = 0, per_cu = 0;
-            HIPCHK(S, hipGetDevice(&dev));
-            HIPCHK(S, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-            HIPCHK(S, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_persist, bt, lds));
-            if ((long)S->R * G > (long)per_cu * cus)
-                return fail(S, GPR_EINVAL, "replicas x groups exceed the workgroups the device holds at once");
-        }
+        int per_cu = 0;
+        HIPCHK(S, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_persist, bt, lds));
+        if (per_cu < 1) return fail(S, GPR_EINVAL, "a workgroup of this shape does not fit on a compute unit");
     }
     S->bt_persist = bt;
     if (groups_per_replica != 0) {
@@ -960,12 +1017,10 @@ extern "C" gpr_status gpr_autotune(gpr_system *S, int32_t nsteps, int32_t *block
         const size_t lds = persist_lds(S->n, S->np, sp);
         if ((int)lds > S->maxlds_persist) continue;
         for (int bt = 256; bt <= 1024 && rc == GPR_OK; bt += 256) {
-            if (G > 1) {
-                int per_cu = 0;
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_persist, bt, lds) != hipSuccess ||
-                    (long)R * G > (long)per_cu * cus)
-                    continue;
-            }
+            int per_cu = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_persist, bt, lds) != hipSuccess ||
+                per_cu < 1 || (G > 1 && per_cu * cus < G))
+                continue;
             S->bt_persist = bt; S->groups = G; S->split = sp;
             hipError_t he = copy_all(false);
             if (he) { rc = fail(S, GPR_EDEVICE, std::string("autotune restore: ") + hipGetErrorString(he)); break; }
@@ -1472,6 +1527,132 @@ extern "C" gpr_status gpr_advance(gpr_system *S, int64_t nsteps, int64_t *first_
     if (err[ERR_LIST]) return fail(S, GPR_EDEVICE, "pair-list capacity exceeded");
     if (err[ERR_BARRIER]) return fail(S, GPR_EDEVICE, "persistent-kernel barrier timed out");
     if (first_exit_check) for (int r = 0; r < S->R; ++r) first_exit_check[r] = f[r];
+    return GPR_OK;
+}
+
+// ------------------------------------------------------------------ several systems in one launch
+// gpr_advance of every system, with the persistent steps of all systems in shared launches:
+// each launch runs up to the next exit check of any of them, then the systems at a check run
+// it.  Workgroups are shared out so as to even out the systems' estimated times per step.
+extern "C" gpr_status gpr_batch_advance(gpr_system *const *systems, int32_t nsys, int64_t nsteps,
+                                        int64_t *const *first_exit_check)
+{
+    if (!systems || nsys < 1 || nsys > MAX_BATCH) return fail(nullptr, GPR_EINVAL, "1 to 8 systems");
+    if (nsteps < 0) return fail(systems[0], GPR_EINVAL, "nsteps < 0");
+    for (int k = 0; k < nsys; ++k) {
+        gpr_system *S = systems[k];
+        if (!S) return fail(nullptr, GPR_EINVAL, "NULL system");
+        for (int j = 0; j < k; ++j)
+            if (systems[j] == S) return fail(S, GPR_EINVAL, "a system appears twice");
+        if (!S->persist_ok) return fail(S, GPR_EINVAL, "system too large for the persistent path");
+        if (S->stream != systems[0]->stream) return fail(S, GPR_EINVAL, "all systems must use one stream");
+    }
+    gpr_system *S0 = systems[0];
+    hipStream_t stream = S0->stream;
+    int bt = 64;
+    size_t lds = 0;
+    std::vector<double> w(nsys);
+    for (int k = 0; k < nsys; ++k) {
+        gpr_system *S = systems[k];
+        bt = std::max(bt, S->bt_persist);
+        lds = std::max(lds, persist_lds(S->n, S->np, S->split));
+        double per = 0.0;
+        for (double x : S->work) per += x;
+        w[k] = per * S->R;
+    }
+    int dev = 0, cus = 0, per_cu = 0;
+    HIPCHK(S0, hipGetDevice(&dev));
+    HIPCHK(S0, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHK(S0, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_persist_batch, bt, lds));
+    const int capacity = per_cu * cus;
+    // sets per system: one each to begin with; then, one set at a time, more for the system
+    // whose replicas would take longest, estimated as (replicas per set) x (time of one
+    // replica-step on one workgroup) / G, that time modelled as 5 us of fixed latency plus
+    // 2.8e-4 us per unit of the per-atom work estimate (both from measured step times).
+    std::vector<int> sets(nsys, 1);
+    int used = 0;
+    for (int k = 0; k < nsys; ++k) used += systems[k]->groups;
+    if (used > capacity) return fail(S0, GPR_EINVAL, "the systems' workgroups do not fit on the device at once");
+    auto est = [&](int k, int ns) {
+        const double t1 = 5.0 + 2.8e-4 * w[k] / systems[k]->R;
+        return (double)((systems[k]->R + ns - 1) / ns) * t1 / systems[k]->groups;
+    };
+    for (;;) {
+        int pick = -1;
+        for (int k = 0; k < nsys; ++k) {
+            if (sets[k] >= systems[k]->R || used + systems[k]->groups > capacity) continue;
+            if (pick < 0 || est(k, sets[k]) > est(pick, sets[pick])) pick = k;
+        }
+        if (pick < 0) break;
+        sets[pick] += 1;
+        used += systems[pick]->groups;
+    }
+    std::vector<PersistItem> items(nsys);
+    std::vector<int> nb(nsys);
+    for (int k = 0; k < nsys; ++k) {
+        bool coop = false;
+        gpr_status rc = persist_item(systems[k], systems[k]->R, bt, lds, sets[k] * systems[k]->groups, items[k], nb[k], coop);
+        if (rc) return rc;
+    }
+    std::vector<int> slot(nsys);            // slot[k]: position of system k's item in the launch
+    PersistBatch pb{};
+    pb.nitems = nsys;
+    int boff = 0, j = 0;
+    for (int pass = 1; pass >= 0; --pass)
+        for (int k = 0; k < nsys; ++k) {
+            if (items[k].xcd != pass) continue;
+            items[k].boff = boff;
+            boff += nb[k];
+            slot[k] = j;
+            pb.it[j++] = items[k];
+        }
+    if (boff > capacity) return fail(S0, GPR_EINVAL, "the systems' workgroups do not fit on the device at once");
+    const int nblocks = boff;
+    std::vector<long long> t(nsys, 0);
+    for (int k = 0; k < nsys; ++k)
+        HIPCHK(systems[k], hipMemsetAsync(systems[k]->fec, 0, sizeof(long long) * systems[k]->R, stream));
+    long long done = 0;
+    while (done < nsteps) {
+        long long kstep = nsteps - done;
+        for (int k = 0; k < nsys; ++k) kstep = std::min<long long>(kstep, systems[k]->tcd - t[k] % systems[k]->tcd);
+        kstep = std::min<long long>(kstep, 1 << 20);
+        for (int k = 0; k < nsys; ++k) {
+            gpr_system *S = systems[k];
+            PersistItem &it = pb.it[slot[k]];
+            it.s0 = S->s;
+            it.nsteps = (int)kstep;
+            it.t0 = (int)t[k];
+            it.sample = 1;
+            it.state_end = (t[k] + kstep) % S->tcd == 0 ? 1 : 0;
+            if (S->groups > 1) HIPCHK(S, hipMemsetAsync(S->d.sync, 0, sizeof(int) * 64 * S->R, stream));
+        }
+        gpr_status rc = launch_persist(S0, pb, nblocks, bt, lds, true, stream);
+        if (rc) return rc;
+        for (int k = 0; k < nsys; ++k) {
+            gpr_system *S = systems[k];
+            S->s += kstep;
+            S->nsamp += count_samples(t[k], t[k] + kstep, S->t_gr);
+            t[k] += kstep;
+            if (t[k] % S->tcd == 0) {
+                rc = check(S, CHK_ADVANCE, S->R, (int)(t[k] / S->tcd));
+                if (rc) return rc;
+            }
+        }
+        done += kstep;
+    }
+    for (int k = 0; k < nsys; ++k) {
+        gpr_system *S = systems[k];
+        std::vector<long long> f(S->R);
+        HIPCHK(S, hipMemcpyAsync(f.data(), S->fec, sizeof(long long) * S->R, hipMemcpyDeviceToHost, stream));
+        int err[4];
+        HIPCHK(S, hipMemcpyAsync(err, S->d.err, sizeof err, hipMemcpyDeviceToHost, stream));
+        HIPCHK(S, hipStreamSynchronize(stream));
+        if (err[ERR_UNSTABLE]) return fail(S, GPR_EUNSTABLE, "non-finite or overflowing state");
+        if (err[ERR_LIST]) return fail(S, GPR_EDEVICE, "pair-list capacity exceeded");
+        if (err[ERR_BARRIER]) return fail(S, GPR_EDEVICE, "persistent-kernel barrier timed out");
+        if (first_exit_check && first_exit_check[k])
+            for (int r = 0; r < S->R; ++r) first_exit_check[k][r] = f[r];
+    }
     return GPR_OK;
 }
 

@@ -30,8 +30,27 @@ __global__ void k_bonded(const Dev *__restrict__ Sp, int r_off, int energy);
 __global__ void k_nonbonded(const Dev *__restrict__ Sp, long long s, int r_off, int energy, int apply_b, int force_build);
 __global__ void k_obs(const Dev *__restrict__ Sp, int r_off, int mode, double *out);
 __global__ void k_state(const Dev *__restrict__ Sp, int r_off);
-__global__ void k_persist(const Dev *__restrict__ Sp, long long s0, int nsteps, int t0, int sample, int state_end,
-                          Split sp, int nrep);
+// one system's share of a persistent launch (see k_persist)
+struct PersistItem {
+    const Dev *dev;     // device descriptor of the system
+    Split sp;           // atom ranges of the workgroups of a replica
+    long long s0;       // global step counter at the first step
+    int nsteps, t0;     // steps of this launch; steps already taken in the current call
+    int sample;         // accumulate worker observables every t_GR steps (t counted from t0)
+    int state_end;      // write each replica's state id at the end
+    int nrep;           // replicas of the system
+    int nsets;          // sets of sp.G workgroups that share the replicas
+    int boff;           // first workgroup of the item in the grid
+    int xcd;            // map a set's workgroups to one XCD (nsets and boff multiples of 8)
+};
+constexpr int MAX_BATCH = 8;
+struct PersistBatch {
+    int nitems;
+    PersistItem it[MAX_BATCH];
+};
+
+__global__ void k_persist(PersistItem it);
+__global__ void k_persist_batch(PersistBatch pb);
 __global__ void k_grad_nb(const Dev *__restrict__ Sp, const double *w);
 __global__ void k_grad_terms(const Dev *__restrict__ Sp, const double *w);
 __global__ void k_grad_finish(const Dev *__restrict__ Sp, double *d_eps, double *d_sigma, double *d_charge, double *d_tk);

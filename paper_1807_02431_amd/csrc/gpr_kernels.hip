@@ -1000,13 +1000,11 @@ __device__ __forceinline__ float2 ld_coh2(const unsigned long long *p)
 // of workers are accumulated by group 0.  With state_end group 0 writes the state id.
 // Workgroups map to replicas so that a replica's groups share an XCD (blockIdx mod 8) when the
 // replica count allows; results do not depend on G or the block size.
-__global__ void __launch_bounds__(1024) k_persist(const Dev *__restrict__ Sp, long long s0, int nsteps, int t0,
-                                                  int sample, int state_end, Split sp, int nrep)
+__device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, int a0, int a1, int r, int g,
+                                                long long s0, int nsteps, int t0, int sample, int state_end)
 {
-    const Dev &S = *Sp;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int np = S.np, n = S.n;
-    const int G = sp.G, lmax = sp.lmax;
     long long *fa = (long long *)lds_raw;                 // [3][lmax]
     long long *red = fa + 3 * lmax;                        // [MAX_OBS * 8 + 8]
     double *vals = (double *)(red + MAX_OBS * 8 + 8);      // [MAX_OBS]
@@ -1020,18 +1018,6 @@ __global__ void __launch_bounds__(1024) k_persist(const Dev *__restrict__ Sp, lo
     int *wscr = (int *)(sph + (n + BLK - 1) / BLK);        // [16][WBLK] build scratch per wave
     __shared__ int sbuf, bbuf, hbuf;
 
-    int r, g;
-    if (G == 1) {
-        r = blockIdx.x; g = 0;
-    } else if (nrep % 8 == 0) {
-        const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
-        r = (slot / G) * 8 + xcd;
-        g = slot % G;
-    } else {
-        r = blockIdx.x / G; g = blockIdx.x % G;
-    }
-    if (r >= nrep) return;
-    const int a0 = sp.bnd[g], a1 = sp.bnd[g + 1];
     const int tid = threadIdx.x, BT = blockDim.x;
     const size_t b = (size_t)r * 3 * np;
     GPR_GLOBAL float *xg = gmut(S.x) + b, *xbg = gmut(S.xb) + b;
@@ -1221,6 +1207,58 @@ __global__ void __launch_bounds__(1024) k_persist(const Dev *__restrict__ Sp, lo
         if (tid == 0) S.state[r] = id;
     }
 }
+
+// Work items of persistent launches: an item is a system whose replicas are shared by nsets
+// sets of sp.G workgroups.  With xcd set (nsets a multiple of 8) the workgroups of a set have
+// equal blockIdx mod 8, i.e. sit on one XCD and share its L2.
+__device__ __forceinline__ bool persist_place(const PersistItem &it, int local, int &set, int &g)
+{
+    const int G = it.sp.G;
+    if (local < 0 || local >= it.nsets * G) return false;
+    if (G == 1) {
+        set = local; g = 0;
+    } else if (it.xcd) {
+        const int x = local % 8, slot = local / 8;
+        set = (slot / G) * 8 + x;
+        g = slot % G;
+    } else {
+        set = local / G; g = local % G;
+    }
+    return true;
+}
+
+// One system, one replica per set (nsets == nrep).
+__global__ void __launch_bounds__(1024) k_persist(PersistItem it)
+{
+    int set, g;
+    if (!persist_place(it, (int)blockIdx.x, set, g) || set >= it.nrep) return;
+    persist_replica(*it.dev, it.sp.G, it.sp.lmax, it.sp.bnd[g], it.sp.bnd[g + 1], set, g, it.s0, it.nsteps, it.t0,
+                    it.sample, it.state_end);
+}
+
+// the per-replica body as a function of its own (one call per replica and launch), so that
+// the loop around it in k_persist_batch does not add to the body's register pressure
+__device__ __noinline__ void persist_replica_call(const Dev *dev, int G, int lmax, int a0, int a1, int r, int g,
+                                                  long long s0, int nsteps, int t0, int sample, int state_end)
+{
+    persist_replica(*dev, G, lmax, a0, a1, r, g, s0, nsteps, t0, sample, state_end);
+}
+
+// Several systems, each item's sets taking its replicas r = set, set + nsets, ... in turn.
+__global__ void __launch_bounds__(1024) k_persist_batch(PersistBatch pb)
+{
+    int k = 0;
+    while (k + 1 < pb.nitems && (int)blockIdx.x >= pb.it[k + 1].boff) ++k;
+    const PersistItem &it = pb.it[k];
+    int set, g;
+    if (!persist_place(it, (int)blockIdx.x - it.boff, set, g)) return;
+    for (int r = set; r < it.nrep; r += it.nsets) {
+        persist_replica_call(it.dev, it.sp.G, it.sp.lmax, it.sp.bnd[g], it.sp.bnd[g + 1], r, g, it.s0, it.nsteps,
+                             it.t0, it.sample, it.state_end);
+        __syncthreads();
+    }
+}
+
 
 // ================================================================== Gen.ParRep bookkeeping
 // Pairwise sum over k = 0..m-1 of f(k): the halving recursion (lower half first) unrolled

@@ -108,6 +108,7 @@ SIGNATURES = {
     "gpr_exit_vote": (C.c_int32, [C.c_int32, _P64, C.c_int64, _P64, C.POINTER(C.c_int32), _P64]),
     "gpr_dephase_fixed": (C.c_int32, [_VP, C.c_int64, C.c_int64, C.POINTER(_Dephase)]),
     "gpr_autotune": (C.c_int32, [_VP, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "gpr_batch_advance": (C.c_int32, [C.POINTER(_VP), C.c_int32, C.c_int64, C.POINTER(_P64)]),
     "gpr_set_params": (C.c_int32, [_VP, _PD, _PD, _PD, _PD]),
     "gpr_energy_forces_dev": (C.c_int32, [_VP, C.c_void_p, C.c_void_p, C.c_void_p]),
     "gpr_energy_backward_dev": (C.c_int32, [_VP, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -373,6 +374,16 @@ class System:
         fec = np.zeros(self.R, np.int64)
         self._c(lib().gpr_advance(self._h, int(nsteps), fec.ctypes.data_as(_P64)))
         return fec
+
+
+def batch_advance(systems, nsteps):
+    """gpr_advance of several systems whose persistent steps share launches; returns each
+    system's first-exit-check array."""
+    hs = (_VP * len(systems))(*[x._h for x in systems])
+    fec = [np.zeros(x.R, np.int64) for x in systems]
+    ptrs = (_P64 * len(systems))(*[f.ctypes.data_as(_P64) for f in fec])
+    _check(lib().gpr_batch_advance(hs, len(systems), int(nsteps), ptrs), systems[0]._h)
+    return fec
 
 
 # ------------------------------------------------------------------ building blocks
