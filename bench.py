@@ -10,7 +10,7 @@ branching plan, the Gelman-Rubin statistics and the exit vote (computed, not act
 that the work per step is fixed).
 
 The product path (persistent kernel) is timed, then the plain one-launch-per-kernel-per-step
-path on the same system and seeds.  Prints one JSON line.
+path on the same system and seeds, launched from the host and replayed from a HIP graph.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -33,6 +33,8 @@ PEAK_HBM_GBS = 8000.0
 FLOP_PAIR = 40          # one in-cutoff nonbonded pair, force only, counted once per unordered pair
 FLOP_BOND, FLOP_ANGLE, FLOP_TORSION, FLOP_RESTRAINT, FLOP_PAIR14 = 25, 60, 110, 12, 45
 FLOP_ATOM_BAOAB = 20    # kicks, drifts and the Ornstein-Uhlenbeck update of one atom
+
+GRAPH_CYCLE = 50        # steps per captured graph of the plain path (one t_GR period)
 
 
 def in_cutoff_pairs(spec, q):
@@ -230,7 +232,7 @@ def main():
     frs = flops_per_replica_step(spec, pairs)
 
     # ------------------------------------------------------------ plain path
-    plain = None
+    plain = plain_graph = None
     if not args.no_plain:
         print("# plain path: warmup %d, timing %d steps" % (args.warmup, args.steps), file=sys.stderr, flush=True)
         pl = gpr.System(spec, path=gpr.PATH_PLAIN, stream=stream)
@@ -243,6 +245,14 @@ def main():
         plain = dict(replica_steps_per_s=R * args.steps / t_pl, atom_steps_per_s=R * n * args.steps / t_pl,
                      ms_per_step=1e3 * t_pl / args.steps, launches_per_step=3,
                      pair_kernel_us=1e3 * nb_ms / max(nb_n, 1))
+        print("# plain path replayed from a HIP graph: warmup %d, timing %d steps" % (args.warmup, args.steps),
+              file=sys.stderr, flush=True)
+        pg = gpr.System(spec, path=gpr.PATH_PLAIN, stream=stream)
+        pg.set_graph(GRAPH_CYCLE)
+        pg.advance(args.warmup)
+        t_pg = timed_advance(pg, args.steps)
+        plain_graph = dict(replica_steps_per_s=R * args.steps / t_pg, ms_per_step=1e3 * t_pg / args.steps,
+                           cycle_steps=GRAPH_CYCLE)
 
     diff = None
     if not args.no_diff:
@@ -274,6 +284,7 @@ def main():
         "vs_baseline": None,
         "speedup_vs_plain": (value / plain["replica_steps_per_s"]) if plain else None,
         "plain_path": plain,
+        "plain_path_graph": plain_graph,
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "receptor-ligand, 2,432 atoms (2,400 restrained receptor + 32 ligand) x 64 replicas, "

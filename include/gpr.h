@@ -220,6 +220,14 @@ gpr_status gpr_set_path(gpr_system *sys, int32_t path);
  * size cannot run.  Results do not depend on the shape. */
 gpr_status gpr_set_launch(gpr_system *sys, int32_t block_threads, int32_t groups_per_replica);
 
+/* Plain path as replays of a HIP graph: with cycle_steps > 0 the plain path's launches of
+ * cycle_steps steps are captured once (per replica count and sampling mode) and replayed;
+ * the kernels then take the step counter and the sampling decision from device memory, so
+ * every replay continues where the last one stopped, and the steps left over are launched
+ * directly.  0 (the default) launches every step from the host.  Results are bit-identical
+ * either way.  EINVAL outside [0, 10000]. */
+gpr_status gpr_set_graph(gpr_system *sys, int32_t cycle_steps);
+
 /* Autotuner of the persistent path's launch shape: every (threads per workgroup in {256, 512,
  * 768, 1024}, workgroups per replica in {1, 2, 4, 8}) that fits the device is timed over nsteps
  * steps from the same saved state, and the fastest becomes the launch shape (written to

@@ -60,6 +60,10 @@ struct gpr_system {
     long long *snap_F = nullptr, *samp_F = nullptr;
     std::vector<long long> resid;
     std::vector<int> done;
+    // plain path as replays of a captured cycle of steps (0: off)
+    int graph_cycle = 0;
+    struct Graph { int nrep, code; hipGraphExec_t exec; };
+    std::vector<Graph> graphs;
     // scratch
     Status *st_dev = nullptr, *st_host = nullptr;
     double *obs_out = nullptr;
@@ -355,6 +359,54 @@ static gpr_status launch_persist(gpr_system *S, PersistBatch &pb, int nblocks, i
     return GPR_OK;
 }
 
+// One plain step on the device clock (code DCLK_*): the kernels read the step and the sampling
+// decision from the device, so the same launches serve every step.
+static gpr_status launch_step_dc(gpr_system *S, int nrep, int code, hipStream_t st)
+{
+    const int BTI = 256, BTB = 256, BTN = 1024;
+    hipLaunchKernelGGL(k_integrate, dim3((S->n + BTI - 1) / BTI, nrep), dim3(BTI), 0, st, S->d_dev, 0LL, 0, code);
+    LAUNCHCHK(S);
+    hipLaunchKernelGGL(k_bonded, dim3((S->n + BTB - 1) / BTB, nrep), dim3(BTB), 3 * BTB * sizeof(long long), st, S->d_dev,
+                       0, code);
+    LAUNCHCHK(S);
+    hipLaunchKernelGGL(k_nonbonded, dim3((S->n * P + BTN - 1) / BTN, nrep), dim3(BTN), S->lds_nb, st, S->d_dev, 0LL, 0,
+                       code, 1, 0);
+    LAUNCHCHK(S);
+    if (code == DCLK_SAMPLE && nrep > 1) {
+        hipLaunchKernelGGL(k_obs, dim3(nrep - 1), dim3(256), S->lds_stage, st, S->d_dev, 1, 3, nullptr);
+        LAUNCHCHK(S);
+    }
+    hipLaunchKernelGGL(k_tick, dim3(1), dim3(1), 0, st, S->d_dev);
+    LAUNCHCHK(S);
+    return GPR_OK;
+}
+
+// The executable graph of graph_cycle device-clocked steps for (nrep, code), captured on a
+// stream of its own the first time it is needed.
+static gpr_status plain_graph(gpr_system *S, int nrep, int code, hipGraphExec_t *out)
+{
+    for (auto &g : S->graphs)
+        if (g.nrep == nrep && g.code == code) { *out = g.exec; return GPR_OK; }
+    hipStream_t cs = nullptr;
+    HIPCHK(S, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    gpr_status rc = GPR_OK;
+    for (int k = 0; k < S->graph_cycle && e == hipSuccess && rc == GPR_OK; ++k) rc = launch_step_dc(S, nrep, code, cs);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &g);
+    hipGraphExec_t ex = nullptr;
+    hipError_t e3 = hipSuccess;
+    if (e == hipSuccess && e2 == hipSuccess && rc == GPR_OK) e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    if (rc) return rc;
+    if (e != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
+        return fail(S, GPR_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2 != hipSuccess ? e2 : e3));
+    S->graphs.push_back({nrep, code, ex});
+    *out = ex;
+    return GPR_OK;
+}
+
 static gpr_status run_steps(gpr_system *S, int nrep, long long nsteps, long long t0, bool sample, bool state_end)
 {
     if (nsteps <= 0) {
@@ -390,6 +442,28 @@ static gpr_status run_steps(gpr_system *S, int nrep, long long nsteps, long long
             done += chunk;
         }
         S->s += nsteps;
+        return GPR_OK;
+    }
+    if (S->graph_cycle > 0) {
+        const int code = (sample && nrep > 1) ? DCLK_SAMPLE : DCLK_NOSAMPLE;
+        hipLaunchKernelGGL(k_set_clock, dim3(1), dim3(1), 0, S->stream, S->d_dev, S->s, t0);
+        LAUNCHCHK(S);
+        long long left = nsteps;
+        if (left >= S->graph_cycle) {
+            hipGraphExec_t ex = nullptr;
+            gpr_status rc = plain_graph(S, nrep, code, &ex);
+            if (rc) return rc;
+            for (; left >= S->graph_cycle; left -= S->graph_cycle) HIPCHK(S, hipGraphLaunch(ex, S->stream));
+        }
+        for (; left > 0; --left) {
+            gpr_status rc = launch_step_dc(S, nrep, code, S->stream);
+            if (rc) return rc;
+        }
+        S->s += nsteps;
+        if (state_end) {
+            hipLaunchKernelGGL(k_state, dim3(nrep), dim3(256), S->lds_stage, S->stream, S->d_dev, 0);
+            LAUNCHCHK(S);
+        }
         return GPR_OK;
     }
     const int BTI = 256;
@@ -468,6 +542,7 @@ extern "C" void gpr_system_destroy(gpr_system *S)
 {
     if (!S) return;
     if (S->stream) (void)hipStreamSynchronize(S->stream);
+    for (auto &g : S->graphs) (void)hipGraphExecDestroy(g.exec);
     for (void *p : S->bufs) (void)hipFree(p);
     for (hipEvent_t e : S->ev_a) (void)hipEventDestroy(e);
     for (hipEvent_t e : S->ev_b) (void)hipEventDestroy(e);
@@ -672,6 +747,7 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
     HIPCHK(S, dalloc(S, &d.guard, 2 * R));
     HIPCHK(S, dalloc(S, &d.need_build, R));
     HIPCHK(S, dalloc(S, &d.last_build, 2 * R));
+    HIPCHK(S, dalloc(S, &d.clock, 2));
     HIPCHK(S, dalloc(S, &d.err, 4));
     HIPCHK(S, dalloc(S, &d.sync, (size_t)R * 64));
     HIPCHK(S, dalloc(S, &d.xchg, (size_t)R * 3 * np));
@@ -1055,6 +1131,19 @@ extern "C" gpr_status gpr_autotune(gpr_system *S, int32_t nsteps, int32_t *block
     S->split = make_split(S->work, S->n, S->np, best_g);
     if (block_threads) *block_threads = best_bt;
     if (groups) *groups = best_g;
+    return GPR_OK;
+}
+
+extern "C" gpr_status gpr_set_graph(gpr_system *S, int32_t cycle_steps)
+{
+    if (!S) return fail(nullptr, GPR_EINVAL, "NULL system");
+    if (cycle_steps < 0 || cycle_steps > 10000) return fail(S, GPR_EINVAL, "cycle_steps must be in [0, 10000]");
+    if (cycle_steps != S->graph_cycle) {
+        HIPCHK(S, hipStreamSynchronize(S->stream));
+        for (auto &g : S->graphs) (void)hipGraphExecDestroy(g.exec);
+        S->graphs.clear();
+        S->graph_cycle = cycle_steps;
+    }
     return GPR_OK;
 }
 

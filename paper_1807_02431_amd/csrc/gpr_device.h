@@ -35,6 +35,10 @@ constexpr double FIX_INV = 2.3283064365386963e-10;  // 2^-32
 constexpr float FMAX_FIX = 1.0e9f;             // |F| beyond this counts as unstable
 constexpr float FAR = 1.0e15f;                 // coordinate of the dummy atom
 constexpr int SPIN_MAX = 1 << 22;              // bound on a barrier wait (then ERR_BARRIER)
+// energy codes of the plain-path kernels: 0 / 1 given by the host; DCLK_* take the step s and
+// the sampling decision from the device clock (so that a captured cycle of steps replays)
+constexpr int DCLK_SAMPLE = 2;                 // workers' observables sampled every t_GR steps
+constexpr int DCLK_NOSAMPLE = 3;
 
 enum { KIND_TOY = 1, KIND_MOL = 2 };
 enum { ST_SIGN_X = 1, ST_BOXES = 2, ST_COM = 3 };
@@ -85,6 +89,7 @@ struct Dev {
     int *guard;                            // [2][R] displacement guard flags by step parity
     int *need_build;                       // [R]
     long long *last_build;                 // [2][R] step of the last pair-list build, by step parity
+    long long *clock;                      // [2]: global step s and steps t of the current call (device-clocked plain steps)
     int *err;                              // [4] error flags
     int *sync;                             // [R][64] per-replica barrier counter and flags (groups > 1)
     float *xchg;                           // [R][3][np] position exchange between a replica's groups

@@ -25,6 +25,8 @@ struct Split {
     int bnd[9];     // group g owns atoms [bnd[g], bnd[g + 1]); every bnd[g] < n is a multiple of 16
 };
 
+__global__ void k_set_clock(const Dev *__restrict__ Sp, long long s, long long t);
+__global__ void k_tick(const Dev *__restrict__ Sp);
 __global__ void k_integrate(const Dev *__restrict__ Sp, long long s, int r_off, int energy);
 __global__ void k_bonded(const Dev *__restrict__ Sp, int r_off, int energy);
 __global__ void k_nonbonded(const Dev *__restrict__ Sp, long long s, int r_off, int energy, int apply_b, int force_build);

@@ -616,10 +616,32 @@ __device__ __forceinline__ void stage_replica(const Dev &S, int r, float4 *xs, f
 }
 
 // ================================================================== plain path kernels
+// Step and energy flag of a plain-path kernel: as given, or from the device clock (codes
+// DCLK_*), where a step samples when (t + 1) is a multiple of t_GR.
+__device__ __forceinline__ void step_args(const Dev &S, long long &s, int &energy)
+{
+    if (energy < DCLK_SAMPLE) return;
+    const bool samp = energy == DCLK_SAMPLE && (S.clock[1] + 1) % S.t_gr == 0;
+    s = S.clock[0];
+    energy = (samp && S.need_energy) ? 1 : 0;
+}
+
+__global__ void k_set_clock(const Dev *__restrict__ Sp, long long s, long long t)
+{
+    Sp->clock[0] = s;
+    Sp->clock[1] = t;
+}
+
+__global__ void k_tick(const Dev *__restrict__ Sp)
+{
+    Sp->clock[0] += 1;
+    Sp->clock[1] += 1;
+}
 // B A O A for every atom of replicas r_off + blockIdx.y; displacement guard; energy reset.
 __global__ void __launch_bounds__(256) k_integrate(const Dev *__restrict__ Sp, long long s, int r_off, int energy)
 {
     const Dev &S = *Sp;
+    step_args(S, s, energy);
     const int r = r_off + blockIdx.y;
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     int *guard = S.guard + (s & 1) * S.R + r;
@@ -652,6 +674,8 @@ __global__ void __launch_bounds__(256) k_integrate(const Dev *__restrict__ Sp, l
 __global__ void __launch_bounds__(256) k_bonded(const Dev *__restrict__ Sp, int r_off, int energy)
 {
     const Dev &S = *Sp;
+    long long s_unused = 0;
+    step_args(S, s_unused, energy);
     extern __shared__ __align__(16) unsigned char lds_raw[];
     long long *fa = (long long *)lds_raw;
     __shared__ long long e_acc;
@@ -691,6 +715,7 @@ __global__ void __launch_bounds__(256) k_bonded(const Dev *__restrict__ Sp, int 
 __global__ void __launch_bounds__(1024) k_nonbonded(const Dev *__restrict__ Sp, long long s, int r_off, int energy, int apply_b,
                                                    int force_build)
 {
+    step_args(*Sp, s, energy);
     const Dev &S = *Sp;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     float4 *xs = (float4 *)lds_raw;
@@ -774,6 +799,7 @@ __global__ void __launch_bounds__(1024) k_nonbonded(const Dev *__restrict__ Sp, 
 __global__ void __launch_bounds__(256) k_obs(const Dev *__restrict__ Sp, int r_off, int mode, double *out)
 {
     const Dev &S = *Sp;
+    if (mode == 3 && (S.clock[1] + 1) % S.t_gr != 0) return;    // device clock: not a sampling step
     extern __shared__ __align__(16) unsigned char lds_raw[];
     float4 *xs = (float4 *)lds_raw;
     __shared__ long long red[MAX_OBS * 8 + 8];
@@ -784,7 +810,7 @@ __global__ void __launch_bounds__(256) k_obs(const Dev *__restrict__ Sp, int r_o
     const float *vg = S.v + (size_t)r * 3 * S.np;
     observables_wg(S, xs, vg, unfix_d(S.E[r]), red, vals, threadIdx.x, blockDim.x);
     if (threadIdx.x == 0) {
-        if (mode == 0) accumulate_obs(S, r, vals);
+        if (mode == 0 || mode == 3) accumulate_obs(S, r, vals);
         else if (mode == 1) for (int j = 0; j < S.nobs; ++j) S.shift[j] = vals[j];
         else for (int j = 0; j < S.nobs; ++j) out[(size_t)r * MAX_OBS + j] = vals[j];
     }

@@ -108,6 +108,7 @@ SIGNATURES = {
     "gpr_exit_vote": (C.c_int32, [C.c_int32, _P64, C.c_int64, _P64, C.POINTER(C.c_int32), _P64]),
     "gpr_dephase_fixed": (C.c_int32, [_VP, C.c_int64, C.c_int64, C.POINTER(_Dephase)]),
     "gpr_autotune": (C.c_int32, [_VP, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "gpr_set_graph": (C.c_int32, [_VP, C.c_int32]),
     "gpr_batch_advance": (C.c_int32, [C.POINTER(_VP), C.c_int32, C.c_int64, C.POINTER(_P64)]),
     "gpr_set_params": (C.c_int32, [_VP, _PD, _PD, _PD, _PD]),
     "gpr_energy_forces_dev": (C.c_int32, [_VP, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -266,6 +267,9 @@ class System:
 
     def set_path(self, path):
         self._c(lib().gpr_set_path(self._h, int(path)))
+
+    def set_graph(self, cycle_steps):
+        self._c(lib().gpr_set_graph(self._h, int(cycle_steps)))
 
     def autotune(self, nsteps=200):
         """Times the persistent path's launch shapes and keeps the fastest; returns it."""
