@@ -228,7 +228,8 @@ static size_t persist_lds(int n, int np, const Split &sp)
     const int lmax = sp.lmax;
     const int nblk = (n + BLK - 1) / BLK;
     return (size_t)3 * lmax * 8 + (MAX_OBS * 8 + 8) * 8 + MAX_OBS * 8 + (size_t)np * 16 + (size_t)np * 8 +
-           (size_t)8 * lmax * 4 + (size_t)nblk * 16 + (size_t)16 * WBLK * 4;
+           (size_t)8 * lmax * 4 + (size_t)nblk * 16 + (size_t)16 * WBLK * 4 + (size_t)32 * ((lmax + 15) / 16) +
+           (size_t)lmax;
 }
 
 // ------------------------------------------------------------------ force-field parameters
@@ -750,7 +751,7 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
     HIPCHK(S, dalloc(S, &d.clock, 2));
     HIPCHK(S, dalloc(S, &d.err, 4));
     HIPCHK(S, dalloc(S, &d.sync, (size_t)R * 64));
-    HIPCHK(S, dalloc(S, &d.xchg, (size_t)R * 3 * np));
+    HIPCHK(S, dalloc(S, &d.xchg, (size_t)R * 6 * np));
     HIPCHK(S, dalloc(S, &d.esum, R));
     HIPCHK(S, dalloc(S, &d.acc, (size_t)R * MAX_OBS * 2));
     HIPCHK(S, dalloc(S, &d.shift, MAX_OBS));

@@ -92,7 +92,7 @@ struct Dev {
     long long *clock;                      // [2]: global step s and steps t of the current call (device-clocked plain steps)
     int *err;                              // [4] error flags
     int *sync;                             // [R][64] per-replica barrier counter and flags (groups > 1)
-    float *xchg;                           // [R][3][np] position exchange between a replica's groups
+    float *xchg;                           // [R][2][3][np] position exchange between a replica's groups (by step parity)
     long long *esum;                       // [R] energy partial sums of a replica's groups
     double *acc;                           // [R][MAX_OBS][2]
     double *shift;                         // [MAX_OBS]
@@ -152,11 +152,10 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
     for (int rnd = 0; rnd < 10; ++rnd) {
-        const uint32_t lo0 = 0xD2511F53u * c.x;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        // one 32 x 32 -> 64-bit product per word (a single v_mad_u64_u32)
+        const unsigned long long p0 = (unsigned long long)c.x * 0xD2511F53u;
+        const unsigned long long p1 = (unsigned long long)c.z * 0xCD9E8D57u;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -177,15 +176,17 @@ __device__ __forceinline__ float unit_open(uint32_t w)
     return (float)(2u * (w >> 9) + 1u) * 5.9604644775390625e-08f;
 }
 
-// Box-Muller: (z0, z1) from (u0, u1), z2 from (u2, u3)
+// Box-Muller: (z0, z1) from (u0, u1), z2 from (u2, u3), on the hardware transcendentals:
+// v_log_f32 gives log2 (so -2 ln u = -2 ln 2 log2 u), v_sin_f32 / v_cos_f32 take their argument
+// in revolutions (sin 2 pi u directly).  Over every uniform the generator produces their
+// largest errors are 1.3e-7 (sin, cos, absolute) and 1.2e-7 (log2, relative).
 __device__ __forceinline__ float3 gauss3(uint4 w)
 {
-    const float ra = sqrtf(-2.0f * logf(unit_open(w.x)));
-    const float rb = sqrtf(-2.0f * logf(unit_open(w.z)));
-    float s1, c1;
-    sincospif(2.0f * unit_open(w.y), &s1, &c1);
-    const float c3 = cospif(2.0f * unit_open(w.w));
-    return make_float3(ra * c1, ra * s1, rb * c3);
+    constexpr float M2LN2 = -1.3862943611198906f;          // -2 ln 2
+    const float ra = __builtin_amdgcn_sqrtf(M2LN2 * __builtin_amdgcn_logf(unit_open(w.x)));
+    const float rb = __builtin_amdgcn_sqrtf(M2LN2 * __builtin_amdgcn_logf(unit_open(w.z)));
+    const float u1 = unit_open(w.y), u3 = unit_open(w.w);
+    return make_float3(ra * __builtin_amdgcn_cosf(u1), ra * __builtin_amdgcn_sinf(u1), rb * __builtin_amdgcn_cosf(u3));
 }
 
 // ------------------------------------------------------------------ fixed point

@@ -44,25 +44,36 @@ struct PosGlob {
 __device__ __forceinline__ float3 neg3(float3 f) { return make_float3(-f.x, -f.y, -f.z); }
 
 // ------------------------------------------------------------------ bonded terms of an atom range
-// Terms touching atoms [a0, a1), by kind (bond, angle, torsion, restraint, 1-4): topology
-// entries [lo[k], lo[k] + cnt[k]) of kind k occupy the slots [off[k], off[k] + cnt[k]) of one
-// flat index space in which every kind starts at a multiple of 64 (so a wave sees one kind).
+// Terms touching atoms [a0, a1), by kind (bond, angle, torsion, restraint, 1-4).  Terms are
+// sorted by their smallest atom and span at most `span` atoms, so those touching [a0, a1) have
+// their smallest atom in [a0 - span, a1).  A plan takes them all (PLAN_ALL), only those lying
+// inside [a0, a1) for sure, smallest atom in [a0, a1 - span) (PLAN_INNER), or the rest
+// (PLAN_EDGE: smallest atom in [a0 - span, a0) or [max(a0, a1 - span), a1)).  Of kind k the
+// entries [lo[k], lo[k] + n1[k]) and [lo2[k], lo2[k] + cnt[k] - n1[k]) occupy the slots
+// [off[k], off[k] + cnt[k]) of one flat index space in which every kind starts at a multiple
+// of 64 (so a wave sees one kind).
+constexpr int PLAN_ALL = 0, PLAN_INNER = 1, PLAN_EDGE = 2;
 struct BondedPlan {
-    int lo[5], cnt[5], off[6];
+    int lo[5], n1[5], lo2[5], cnt[5], off[6];
 };
 
-__device__ __forceinline__ BondedPlan bonded_plan(const Dev &S, int a0, int a1)
+__device__ __forceinline__ BondedPlan bonded_plan(const Dev &S, int a0, int a1, int part = PLAN_ALL)
 {
     const Topo &T = S.tp;
     BondedPlan bp;
     auto range = [&](int k, int nterm, const int *start, int span) {
-        int lo = 0, hi = 0;
+        int lo = 0, n1 = 0, lo2 = 0, n2 = 0;
         if (nterm) {
-            lo = gconst(start)[max(0, a0 - span)];
-            hi = gconst(start)[a1];
+            const GPR_GLOBAL int *st = gconst(start);
+            const int b0 = st[max(0, a0 - span)], b1 = st[a0], b2 = st[max(a0, a1 - span)], b3 = st[a1];
+            if (part == PLAN_ALL) { lo = b0; n1 = b3 - b0; }
+            else if (part == PLAN_INNER) { lo = b1; n1 = b2 - b1; }
+            else { lo = b0; n1 = b1 - b0; lo2 = b2; n2 = b3 - b2; }
         }
         bp.lo[k] = lo;
-        bp.cnt[k] = hi - lo;
+        bp.n1[k] = n1;
+        bp.lo2[k] = lo2;
+        bp.cnt[k] = n1 + n2;
     };
     range(0, T.nb, T.b_start, T.b_span);
     range(1, T.na, T.a_start, T.a_span);
@@ -104,14 +115,14 @@ __device__ void bonded_range(const Dev &S, const BondedPlan &bp, const Pos &pos,
             // kind and topology index of the slot (static indices into the plan: no scratch)
             int k = -1, t = 0;
             if (slot < total) {
-                int local, cnt, lo;
-                if (slot < bp.off[1]) { k = 0; local = slot; cnt = bp.cnt[0]; lo = bp.lo[0]; }
-                else if (slot < bp.off[2]) { k = 1; local = slot - bp.off[1]; cnt = bp.cnt[1]; lo = bp.lo[1]; }
-                else if (slot < bp.off[3]) { k = 2; local = slot - bp.off[2]; cnt = bp.cnt[2]; lo = bp.lo[2]; }
-                else if (slot < bp.off[4]) { k = 3; local = slot - bp.off[3]; cnt = bp.cnt[3]; lo = bp.lo[3]; }
-                else { k = 4; local = slot - bp.off[4]; cnt = bp.cnt[4]; lo = bp.lo[4]; }
+                int local, cnt, lo, n1, lo2;
+                if (slot < bp.off[1]) { k = 0; local = slot; cnt = bp.cnt[0]; lo = bp.lo[0]; n1 = bp.n1[0]; lo2 = bp.lo2[0]; }
+                else if (slot < bp.off[2]) { k = 1; local = slot - bp.off[1]; cnt = bp.cnt[1]; lo = bp.lo[1]; n1 = bp.n1[1]; lo2 = bp.lo2[1]; }
+                else if (slot < bp.off[3]) { k = 2; local = slot - bp.off[2]; cnt = bp.cnt[2]; lo = bp.lo[2]; n1 = bp.n1[2]; lo2 = bp.lo2[2]; }
+                else if (slot < bp.off[4]) { k = 3; local = slot - bp.off[3]; cnt = bp.cnt[3]; lo = bp.lo[3]; n1 = bp.n1[3]; lo2 = bp.lo2[3]; }
+                else { k = 4; local = slot - bp.off[4]; cnt = bp.cnt[4]; lo = bp.lo[4]; n1 = bp.n1[4]; lo2 = bp.lo2[4]; }
                 if (local >= cnt) k = -1;
-                t = lo + local;
+                t = local < n1 ? lo + local : lo2 + (local - n1);
             }
             kind[u] = k;
             idx[u] = make_int4(0, 0, 0, 0);
@@ -243,8 +254,8 @@ __device__ __forceinline__ float wave16_max(float v)
 // excluded partners at that point.  UNR blocks are read at a time (more registers, fewer
 // exposed LDS latencies); the plain path's pair kernel uses 1 to keep its occupancy.
 template <int UNR>
-__device__ __noinline__ void build_wave(const Dev &S, int r, int i, int q, bool valid, const GPR_LDS gv_f4 *xs,
-                                        const GPR_LDS gv_f4 *sph, GPR_LDS int *wblk, bool allpairs)
+__device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool valid, const GPR_LDS gv_f4 *xs,
+                                       const GPR_LDS gv_f4 *sph, GPR_LDS int *wblk, bool allpairs)
 {
     const int n = S.n;
     const size_t stride = (size_t)S.np * P;
@@ -252,7 +263,7 @@ __device__ __noinline__ void build_wave(const Dev &S, int r, int i, int q, bool 
     // bounding sphere of the wave's valid atoms
     const float big = 3.0e38f;
     const float mnx = wave16_min(valid ? pi.x : big), mxx = wave16_max(valid ? pi.x : -big);
-    if (!(mnx <= mxx)) return;                                  // no valid lane in this wave
+    if (!(mnx <= mxx)) return 0;                                // no valid lane in this wave
     const float mny = wave16_min(valid ? pi.y : big), mxy = wave16_max(valid ? pi.y : -big);
     const float mnz = wave16_min(valid ? pi.z : big), mxz = wave16_max(valid ? pi.z : -big);
     const float cx = 0.5f * (mnx + mxx), cy = 0.5f * (mny + mxy), cz = 0.5f * (mnz + mxz);
@@ -359,7 +370,7 @@ __device__ __noinline__ void build_wave(const Dev &S, int r, int i, int q, bool 
         }
         emit(base);
     }
-    if (!valid) return;
+    if (!valid) return 0;
     const int ng = (cnt + 3) >> 2;
     if ((cnt & 3) != 0 && cnt < cap) {
         for (int k = cnt & 3; k < 4; ++k) word |= (unsigned long long)n << (16 * k);
@@ -367,6 +378,7 @@ __device__ __noinline__ void build_wave(const Dev &S, int r, int i, int q, bool 
     }
     gmut(S.nbc)[(size_t)r * stride + (size_t)i * P + q] = (unsigned short)min(ng, S.Kg);
     if (cnt > cap) atomicOr(&S.err[ERR_LIST], 1);
+    return min(ng, S.Kg);
 }
 
 // ------------------------------------------------------------------ nonbonded partial sum of one lane
@@ -1026,6 +1038,36 @@ __device__ __forceinline__ float2 ld_coh2(const unsigned long long *p)
 // of workers are accumulated by group 0.  With state_end group 0 writes the state id.
 // Workgroups map to replicas so that a replica's groups share an XCD (blockIdx mod 8) when the
 // replica count allows; results do not depend on G or the block size.
+// Pair-loop order of a group's nl atoms.  A task of the pair loop is 16 atoms on the 64 lanes
+// of a wave and runs as long as its longest list, so the atoms go longest list first (key: the
+// atom's longest sub-list, in words): tasks of similar lists, taken heaviest first.  perm has
+// 16 * ceil(nl / 16) slots; those past nl hold 0xFFFF.  Forces do not depend on the order: an
+// atom's four lanes stay together and sum its own sub-lists in their fixed order.
+__device__ void order_atoms(const unsigned char *key, unsigned short *perm, int *hist, int nl, int tid, int nthr)
+{
+    const int nt = (nl + 15) >> 4;
+    for (int k = tid; k < 16 * nt; k += nthr) perm[k] = 0xFFFF;
+    for (int k = tid; k < 64; k += nthr) hist[k] = 0;
+    __syncthreads();
+    for (int l = tid; l < nl; l += nthr) atomicAdd(&hist[63 - min((int)key[l], 63)], 1);
+    __syncthreads();
+    if (tid < 64) {                                        // exclusive prefix sum of the bins
+        const int c = hist[tid];
+        int x = c;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(x, d, 64);
+            if (tid >= d) x += y;
+        }
+        hist[tid] = x - c;
+    }
+    __syncthreads();
+    for (int l = tid; l < nl; l += nthr) {
+        const int k = atomicAdd(&hist[63 - min((int)key[l], 63)], 1);
+        perm[k] = (unsigned short)l;
+    }
+    __syncthreads();
+}
+
 __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, int a0, int a1, int r, int g,
                                                 long long s0, int nsteps, int t0, int sample, int state_end)
 {
@@ -1042,7 +1084,9 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
     float *xbl = sdl + lmax;                               // [3][lmax] own positions at the last list build
     float4 *sph = (float4 *)(xbl + 3 * lmax);              // [nblk]
     int *wscr = (int *)(sph + (n + BLK - 1) / BLK);        // [16][WBLK] build scratch per wave
-    __shared__ int sbuf, bbuf, hbuf;
+    unsigned short *perm = (unsigned short *)(wscr + 16 * WBLK);   // [16 ceil(lmax / 16)] pair-loop order
+    unsigned char *keyl = (unsigned char *)(perm + 16 * ((lmax + 15) >> 4));   // [lmax] list length, words
+    __shared__ int sbuf, bbuf, hbuf, hist[64], ptask;
 
     const int tid = threadIdx.x, BT = blockDim.x;
     const size_t b = (size_t)r * 3 * np;
@@ -1052,8 +1096,10 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
     const GPR_GLOBAL float4 *prm = gconst(S.prm);
     const GPR_GLOBAL float *sdv = gconst(S.sd);
     int *sync = S.sync + (size_t)r * 64;
-    unsigned long long *xch_xy = (unsigned long long *)(S.xchg + b);   // [np] (x, y)
-    float *xch_z = S.xchg + b + 2 * np;                                   // [np] z
+    // position exchange, one buffer per step parity: a group writes step s + 1 only after the
+    // barrier of step s, which every group passes after reading step s - 1
+    unsigned long long *xch_xy0 = (unsigned long long *)(S.xchg + 2 * b);        // [2][np] (x, y)
+    float *xch_z0 = S.xchg + 2 * b + 4 * np;                                        // [2][np] z
     int gen = 0;
 
     stage_replica(S, r, xs, pp, tid, BT);
@@ -1072,7 +1118,22 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
     long long lastb = S.last_build[(s0 & 1) * S.R + r];     // step of the last pair-list build
     __syncthreads();
     const bool toy = S.kind == KIND_TOY;
-    const BondedPlan bplan = bonded_plan(S, a0, a1);
+    const int nl = a1 - a0, nslot = 16 * ((nl + 15) >> 4);
+    if (!toy) {
+        // the lists in place (built by an earlier launch) give the first order
+        const GPR_GLOBAL unsigned short *cg = gconst(S.nbc) + (size_t)r * np * P + (size_t)a0 * P;
+        for (int l = tid; l < nl; l += BT) {
+            const int c = max(max(cg[l * P], cg[l * P + 1]), max(cg[l * P + 2], cg[l * P + 3]));
+            keyl[l] = (unsigned char)min(c, 255);
+        }
+        order_atoms(keyl, perm, hist, nl, tid, BT);
+    }
+    // with several groups the bonded terms inside the group's range run while its first waves
+    // wait at the barrier and fetch the other groups' positions; the rest run after
+    const bool split = G > 1 && !toy && BT >= 128;
+    const BondedPlan bplan = bonded_plan(S, a0, a1, split ? PLAN_EDGE : PLAN_ALL);
+    const BondedPlan bpin = bonded_plan(S, a0, a1, PLAN_INNER);
+    const int XT = BT >= 512 ? 128 : 64;                    // exchange threads (whole waves)
     long long *eacc = red + MAX_OBS * 8;
     bool alive = true;
 
@@ -1081,6 +1142,8 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
         const int tl = t0 + step + 1;
         const bool samp = sample && r >= 1 && (tl % S.t_gr == 0);
         const bool energy = samp && S.need_energy;
+        unsigned long long *xch_xy = xch_xy0 + (s & 1) * np;
+        float *xch_z = xch_z0 + (s & 1) * np;
         int hit = 0, bad = 0;
         for (int a = a0 + tid; a < a1; a += BT) {
             const int l = a - a0;
@@ -1103,15 +1166,68 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
             // displacement-guard flags in three rotating slots; group 0 clears the slot of the next step
             if (hit) __hip_atomic_fetch_or(sync + 16 + 16 * (int)(s % 3), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (g == 0 && tid == 0) __hip_atomic_store(sync + 16 + 16 * (int)((s + 1) % 3), 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            alive = group_barrier(sync, G * ++gen, S.err, &bbuf);
-            if (!alive) break;
-            if (tid == 0) hbuf = __hip_atomic_load(sync + 16 + 16 * (int)(s % 3), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            for (int a = tid; a < n; a += BT) {
-                if (a >= a0 && a < a1) continue;
-                const float2 xy = ld_coh2(xch_xy + a);
-                xs[a].x = xy.x; xs[a].y = xy.y; xs[a].z = ld_coh(xch_z + a);
+            if (split) {
+                // arrive; the first XT threads wait (bounded spin, one per wave) and fetch the
+                // other groups' positions while the others add the inner bonded terms
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                __syncthreads();                     // own positions stored, forces read
+                if (tid == 0) {
+                    __hip_atomic_fetch_add(sync, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    bbuf = 1;
+                }
+                for (int k = tid; k < 3 * lmax; k += BT) fa[k] = 0;
+                if (tid == 0) { *eacc = 0; ptask = 0; }
+                __syncthreads();
+                const int target = G * ++gen;
+                if (tid < XT) {
+                    if ((tid & 63) == 0) {
+                        int spins = 0;
+                        while (__hip_atomic_load(sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                            if (++spins > SPIN_MAX) {
+                                atomicOr(S.err + ERR_BARRIER, 1);
+                                bbuf = 0;
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(1);
+                        }
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    if (tid == 0) hbuf = __hip_atomic_load(sync + 16 + 16 * (int)(s % 3), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    // all loads of a batch in flight before the first LDS write
+                    constexpr int XU = 4;
+                    for (int a0x = 0; a0x < n; a0x += XU * XT) {
+                        float2 xy[XU];
+                        float z[XU];
+#pragma unroll
+                        for (int u = 0; u < XU; ++u) {
+                            const int a = a0x + u * XT + tid;
+                            const bool other = a < n && (a < a0 || a >= a1);
+                            xy[u] = other ? ld_coh2(xch_xy + a) : make_float2(0.f, 0.f);
+                            z[u] = other ? ld_coh(xch_z + a) : 0.f;
+                        }
+#pragma unroll
+                        for (int u = 0; u < XU; ++u) {
+                            const int a = a0x + u * XT + tid;
+                            if (a < n && (a < a0 || a >= a1)) { xs[a].x = xy[u].x; xs[a].y = xy[u].y; xs[a].z = z[u]; }
+                        }
+                    }
+                } else {
+                    bonded_range(S, bpin, PosLDS{xs}, a0, a1, fa, lmax, energy ? eacc : nullptr, tid - XT, BT - XT);
+                }
+                __syncthreads();
+                alive = bbuf != 0;
+                if (!alive) break;
+            } else {
+                alive = group_barrier(sync, G * ++gen, S.err, &bbuf);
+                if (!alive) break;
+                if (tid == 0) hbuf = __hip_atomic_load(sync + 16 + 16 * (int)(s % 3), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                for (int a = tid; a < n; a += BT) {
+                    if (a >= a0 && a < a1) continue;
+                    const float2 xy = ld_coh2(xch_xy + a);
+                    xs[a].x = xy.x; xs[a].y = xy.y; xs[a].z = ld_coh(xch_z + a);
+                }
+                __syncthreads();
             }
-            __syncthreads();
             any_hit = hbuf;
         } else {
             any_hit = __syncthreads_or(hit);
@@ -1126,18 +1242,25 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
                 if (L0 + (tid & ~63) >= a1 * P) continue;          // whole wave past the group's atoms
                 const int L = L0 + tid, i = L / P, q = L % P;
                 const bool valid = L < a1 * P;
-                build_wave<4>(S, r, i, q, valid, (const GPR_LDS gv_f4 *)xs, (const GPR_LDS gv_f4 *)sph,
-                           (GPR_LDS int *)wscr + (tid >> 6) * WBLK, false);
+                const int ngw = build_wave<4>(S, r, i, q, valid, (const GPR_LDS gv_f4 *)xs,
+                                              (const GPR_LDS gv_f4 *)sph, (GPR_LDS int *)wscr + (tid >> 6) * WBLK,
+                                              false);
+                int kq = max(ngw, __shfl_xor(ngw, 1, 64));
+                kq = max(kq, __shfl_xor(kq, 2, 64));
                 if (valid && q == 0) {
                     const int l = i - a0;
                     xbl[l] = xs[i].x; xbl[lmax + l] = xs[i].y; xbl[2 * lmax + l] = xs[i].z;
+                    keyl[l] = (unsigned char)min(kq, 255);
                 }
             }
+            order_atoms(keyl, perm, hist, nl, tid, BT);
             need = false;
         }
-        for (int k = tid; k < 3 * lmax; k += BT) fa[k] = 0;
-        if (tid == 0) *eacc = 0;
-        __syncthreads();
+        if (!split) {
+            for (int k = tid; k < 3 * lmax; k += BT) fa[k] = 0;
+            if (tid == 0) { *eacc = 0; ptask = 0; }
+            __syncthreads();
+        }
         if (toy) {
             if (tid == 0 && a0 == 0 && a1 > 0) {
                 float fx, fy;
@@ -1147,19 +1270,26 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
                 if (energy) *eacc = fix_f(u);
             }
         } else {
+            // bonded terms, then the pair loop, whose tasks (16 atoms each, longest lists first)
+            // the waves take from a shared counter as they come free
             bonded_range(S, bplan, PosLDS{xs}, a0, a1, fa, lmax, energy ? eacc : nullptr, tid, BT);
-            for (int L0 = a0 * P; L0 < a1 * P; L0 += BT) {
-                const int L = L0 + tid;
-                const int i = L / P, q = L % P;
+            const int ntask = nslot >> 4;
+            for (;;) {
+                int t = 0;
+                if ((tid & 63) == 0) t = atomicAdd(&ptask, 1);
+                t = __builtin_amdgcn_readfirstlane(__shfl(t, 0, 64));
+                if (t >= ntask) break;
+                const int q = tid & 3;
+                const int l = perm[16 * t + ((tid & 63) >> 2)];
                 long long eatom = 0;
-                if (L < a1 * P) {
+                if (l != 0xFFFF) {
+                    const int i = a0 + l;
                     float4 f = nb_lane(S, r, i, q, xs, pp, energy);
                     f.x = quad_sum(f.x);
                     f.y = quad_sum(f.y);
                     f.z = quad_sum(f.z);
                     if (energy) f.w = quad_sum(f.w);
                     if (q == 0) {
-                        const int l = i - a0;
                         lds_add(&fa[l], fix_f(f.x));
                         lds_add(&fa[lmax + l], fix_f(f.y));
                         lds_add(&fa[2 * lmax + l], fix_f(f.z));
