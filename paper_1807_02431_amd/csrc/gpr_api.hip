@@ -342,12 +342,12 @@ static gpr_status persist_item(gpr_system *S, int nrep, int bt, size_t lds, int 
     return GPR_OK;
 }
 
-// A single item with a set per replica runs k_persist; anything else (several systems, or
-// sets that take replicas in turn) runs k_persist_batch.
+// One item whose sets each take one replica (roff + set) runs k_persist; anything else
+// (several systems, or sets that take replicas in turn) runs k_persist_batch.
 static gpr_status launch_persist(gpr_system *S, PersistBatch &pb, int nblocks, int bt, size_t lds, bool coop,
-                                 hipStream_t stream)
+                                 hipStream_t stream, bool one_round = false)
 {
-    const bool single = pb.nitems == 1 && pb.it[0].nsets >= pb.it[0].nrep;
+    const bool single = pb.nitems == 1 && (one_round || pb.it[0].nsets >= pb.it[0].nrep);
     const void *fn = single ? (const void *)k_persist : (const void *)k_persist_batch;
     void *args_single[] = {(void *)&pb.it[0]};
     void *args_batch[] = {(void *)&pb};
@@ -425,6 +425,9 @@ static gpr_status run_steps(gpr_system *S, int nrep, long long nsteps, long long
         const size_t lds = persist_lds(S->n, S->np, S->split);
         gpr_status rc = persist_item(S, nrep, S->bt_persist, lds, -1, pb.it[0], nblocks, coop);
         if (rc) return rc;
+        // more replicas than sets that fit at once: rounds of launches, each set taking one
+        // replica per launch (replicas are independent between checks)
+        const int rounds = (nrep + pb.it[0].nsets - 1) / pb.it[0].nsets;
         long long done = 0;
         while (done < nsteps) {
             const int chunk = (int)std::min<long long>(nsteps - done, 1 << 20);
@@ -435,11 +438,14 @@ static gpr_status run_steps(gpr_system *S, int nrep, long long nsteps, long long
             it.t0 = (int)(t0 + done);
             it.sample = sample ? 1 : 0;
             it.state_end = (state_end && last) ? 1 : 0;
-            if (S->groups > 1) HIPCHK(S, hipMemsetAsync(S->d.sync, 0, sizeof(int) * 64 * S->R, S->stream));
-            HIPCHK(S, prof_begin(S));
-            rc = launch_persist(S, pb, nblocks, S->bt_persist, lds, coop, S->stream);
-            if (rc) return rc;
-            HIPCHK(S, prof_end(S));
+            for (int k = 0; k < rounds; ++k) {
+                it.roff = k * it.nsets;
+                if (S->groups > 1) HIPCHK(S, hipMemsetAsync(S->d.sync, 0, sizeof(int) * 64 * S->R, S->stream));
+                HIPCHK(S, prof_begin(S));
+                rc = launch_persist(S, pb, nblocks, S->bt_persist, lds, coop, S->stream, true);
+                if (rc) return rc;
+                HIPCHK(S, prof_end(S));
+            }
             done += chunk;
         }
         S->s += nsteps;

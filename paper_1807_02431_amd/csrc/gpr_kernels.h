@@ -42,6 +42,7 @@ struct PersistItem {
     int state_end;      // write each replica's state id at the end
     int nrep;           // replicas of the system
     int nsets;          // sets of sp.G workgroups that share the replicas
+    int roff;           // k_persist: set k takes replica roff + k
     int boff;           // first workgroup of the item in the grid
     int xcd;            // map a set's workgroups to one XCD (nsets and boff multiples of 8)
 };

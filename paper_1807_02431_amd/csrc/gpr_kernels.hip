@@ -1383,21 +1383,33 @@ __device__ __forceinline__ bool persist_place(const PersistItem &it, int local, 
     return true;
 }
 
-// One system, one replica per set (nsets == nrep).
+// One system, one replica per set: replicas roff, roff + 1, ... (a system with more replicas
+// than sets that fit at once takes several launches, each with the body inlined).
 __global__ void __launch_bounds__(1024) k_persist(PersistItem it)
 {
     int set, g;
-    if (!persist_place(it, (int)blockIdx.x, set, g) || set >= it.nrep) return;
-    persist_replica(*it.dev, it.sp.G, it.sp.lmax, it.sp.bnd[g], it.sp.bnd[g + 1], set, g, it.s0, it.nsteps, it.t0,
-                    it.sample, it.state_end);
+    if (!persist_place(it, (int)blockIdx.x, set, g) || set + it.roff >= it.nrep) return;
+    persist_replica(*it.dev, it.sp.G, it.sp.lmax, it.sp.bnd[g], it.sp.bnd[g + 1], set + it.roff, g, it.s0, it.nsteps,
+                    it.t0, it.sample, it.state_end);
+}
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ long long uni64(long long v)
+{
+    const int lo = uni((int)(unsigned)v), hi = uni((int)(v >> 32));
+    return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
 // the per-replica body as a function of its own (one call per replica and launch), so that
-// the loop around it in k_persist_batch does not add to the body's register pressure
+// the loop around it in k_persist_batch does not add to the body's register pressure.  The
+// arguments of a call arrive in vector registers; they are wave-uniform, and made so again,
+// so that the values and branches that depend on them stay scalar.
 __device__ __noinline__ void persist_replica_call(const Dev *dev, int G, int lmax, int a0, int a1, int r, int g,
                                                   long long s0, int nsteps, int t0, int sample, int state_end)
 {
-    persist_replica(*dev, G, lmax, a0, a1, r, g, s0, nsteps, t0, sample, state_end);
+    const Dev *d = (const Dev *)uni64((long long)dev);
+    persist_replica(*d, uni(G), uni(lmax), uni(a0), uni(a1), uni(r), uni(g), uni64(s0), uni(nsteps), uni(t0),
+                    uni(sample), uni(state_end));
 }
 
 // Several systems, each item's sets taking its replicas r = set, set + nsets, ... in turn.
