@@ -62,7 +62,7 @@ struct gpr_system {
     std::vector<int> done;
     // plain path as replays of a captured cycle of steps (0: off)
     int graph_cycle = 0;
-    struct Graph { int nrep, code; hipGraphExec_t exec; };
+    struct Graph { int nrep, code, phase; hipGraphExec_t exec; };
     std::vector<Graph> graphs;
     // scratch
     Status *st_dev = nullptr, *st_host = nullptr;
@@ -290,7 +290,7 @@ static gpr_status launch_forces(gpr_system *S, int r_off, int nrep, long long s,
         HIPCHK(S, hipMemsetAsync(S->d.E + r_off, 0, sizeof(long long) * nrep, S->stream));
     }
     dim3 gb((S->n + BTB - 1) / BTB, nrep);
-    hipLaunchKernelGGL(k_bonded, gb, dim3(BTB), 3 * BTB * sizeof(long long), S->stream, S->d_dev, r_off, energy);
+    hipLaunchKernelGGL(k_bonded, gb, dim3(BTB), 3 * BTB * sizeof(long long), S->stream, S->d_dev, s, r_off, energy);
     LAUNCHCHK(S);
     dim3 gn((S->n * P + BTN - 1) / BTN, nrep);
     if (timed) HIPCHK(S, prof_begin(S));
@@ -360,39 +360,50 @@ static gpr_status launch_persist(gpr_system *S, PersistBatch &pb, int nblocks, i
     return GPR_OK;
 }
 
-// One plain step on the device clock (code DCLK_*): the kernels read the step and the sampling
-// decision from the device, so the same launches serve every step.
-static gpr_status launch_step_dc(gpr_system *S, int nrep, int code, hipStream_t st)
+// Step k of a captured cycle on the device clock (code DCLK_*): the kernels read the cycle's
+// first step and local step from the device, so every replay continues where the last one
+// stopped.  The observables of the workers: with phase >= 0 (the local step at the cycle's
+// start, mod t_GR) at the steps that sample; with phase < 0 a launch every step that returns
+// unless the step samples.
+static gpr_status launch_step_dc(gpr_system *S, int nrep, int code, int phase, int k, hipStream_t st)
 {
     const int BTI = 256, BTB = 256, BTN = 1024;
-    hipLaunchKernelGGL(k_integrate, dim3((S->n + BTI - 1) / BTI, nrep), dim3(BTI), 0, st, S->d_dev, 0LL, 0, code);
+    hipLaunchKernelGGL(k_integrate, dim3((S->n + BTI - 1) / BTI, nrep), dim3(BTI), 0, st, S->d_dev, (long long)k, 0, code);
     LAUNCHCHK(S);
     hipLaunchKernelGGL(k_bonded, dim3((S->n + BTB - 1) / BTB, nrep), dim3(BTB), 3 * BTB * sizeof(long long), st, S->d_dev,
-                       0, code);
+                       (long long)k, 0, code);
     LAUNCHCHK(S);
-    hipLaunchKernelGGL(k_nonbonded, dim3((S->n * P + BTN - 1) / BTN, nrep), dim3(BTN), S->lds_nb, st, S->d_dev, 0LL, 0,
-                       code, 1, 0);
+    hipLaunchKernelGGL(k_nonbonded, dim3((S->n * P + BTN - 1) / BTN, nrep), dim3(BTN), S->lds_nb, st, S->d_dev,
+                       (long long)k, 0, code, 1, 0);
     LAUNCHCHK(S);
     if (code == DCLK_SAMPLE && nrep > 1) {
-        hipLaunchKernelGGL(k_obs, dim3(nrep - 1), dim3(256), S->lds_stage, st, S->d_dev, 1, 3, nullptr);
-        LAUNCHCHK(S);
+        if (phase < 0) {
+            hipLaunchKernelGGL(k_obs, dim3(nrep - 1), dim3(256), S->lds_stage, st, S->d_dev, 1, 3, nullptr, k);
+            LAUNCHCHK(S);
+        } else if ((phase + k + 1) % S->t_gr == 0) {
+            hipLaunchKernelGGL(k_obs, dim3(nrep - 1), dim3(256), S->lds_stage, st, S->d_dev, 1, 0, nullptr, 0);
+            LAUNCHCHK(S);
+        }
     }
-    hipLaunchKernelGGL(k_tick, dim3(1), dim3(1), 0, st, S->d_dev);
-    LAUNCHCHK(S);
     return GPR_OK;
 }
 
-// The executable graph of graph_cycle device-clocked steps for (nrep, code), captured on a
-// stream of its own the first time it is needed.
-static gpr_status plain_graph(gpr_system *S, int nrep, int code, hipGraphExec_t *out)
+// The executable graph of graph_cycle device-clocked steps and the clock advance for
+// (nrep, code, phase), captured on a stream of its own the first time it is needed.
+static gpr_status plain_graph(gpr_system *S, int nrep, int code, int phase, hipGraphExec_t *out)
 {
     for (auto &g : S->graphs)
-        if (g.nrep == nrep && g.code == code) { *out = g.exec; return GPR_OK; }
+        if (g.nrep == nrep && g.code == code && g.phase == phase) { *out = g.exec; return GPR_OK; }
     hipStream_t cs = nullptr;
     HIPCHK(S, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     gpr_status rc = GPR_OK;
-    for (int k = 0; k < S->graph_cycle && e == hipSuccess && rc == GPR_OK; ++k) rc = launch_step_dc(S, nrep, code, cs);
+    for (int k = 0; k < S->graph_cycle && e == hipSuccess && rc == GPR_OK; ++k)
+        rc = launch_step_dc(S, nrep, code, phase, k, cs);
+    if (e == hipSuccess && rc == GPR_OK) {
+        hipLaunchKernelGGL(k_tick, dim3(1), dim3(1), 0, cs, S->d_dev, (long long)S->graph_cycle);
+        e = hipGetLastError();
+    }
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(cs, &g);
     hipGraphExec_t ex = nullptr;
@@ -403,8 +414,30 @@ static gpr_status plain_graph(gpr_system *S, int nrep, int code, hipGraphExec_t 
     if (rc) return rc;
     if (e != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
         return fail(S, GPR_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2 != hipSuccess ? e2 : e3));
-    S->graphs.push_back({nrep, code, ex});
+    S->graphs.push_back({nrep, code, phase, ex});
     *out = ex;
+    return GPR_OK;
+}
+
+// nsteps plain steps launched from the host, local steps counted from t0
+static gpr_status plain_steps(gpr_system *S, int nrep, long long nsteps, long long t0, bool sample)
+{
+    const int BTI = 256;
+    dim3 gi((S->n + BTI - 1) / BTI, nrep);
+    for (long long k = 0; k < nsteps; ++k) {
+        const long long tl = t0 + k + 1;
+        const bool samp = sample && nrep > 1 && (tl % S->t_gr == 0);
+        const int energy = (samp && S->d.need_energy) ? 1 : 0;
+        hipLaunchKernelGGL(k_integrate, gi, dim3(BTI), 0, S->stream, S->d_dev, S->s, 0, energy);
+        LAUNCHCHK(S);
+        gpr_status rc = launch_forces(S, 0, nrep, S->s, energy, 1, 0, true);
+        if (rc) return rc;
+        S->s += 1;
+        if (samp) {
+            hipLaunchKernelGGL(k_obs, dim3(nrep - 1), dim3(256), S->lds_stage, S->stream, S->d_dev, 1, 0, nullptr, 0);
+            LAUNCHCHK(S);
+        }
+    }
     return GPR_OK;
 }
 
@@ -451,44 +484,24 @@ static gpr_status run_steps(gpr_system *S, int nrep, long long nsteps, long long
         S->s += nsteps;
         return GPR_OK;
     }
-    if (S->graph_cycle > 0) {
+    // whole cycles replayed from a captured graph, the steps left over launched from the host
+    long long left = nsteps, tcur = t0;
+    if (S->graph_cycle > 0 && left >= S->graph_cycle) {
         const int code = (sample && nrep > 1) ? DCLK_SAMPLE : DCLK_NOSAMPLE;
+        const int phase = (code == DCLK_SAMPLE && S->graph_cycle % S->t_gr == 0) ? (int)(t0 % S->t_gr) : -1;
+        hipGraphExec_t ex = nullptr;
+        gpr_status rc = plain_graph(S, nrep, code, phase, &ex);
+        if (rc) return rc;
         hipLaunchKernelGGL(k_set_clock, dim3(1), dim3(1), 0, S->stream, S->d_dev, S->s, t0);
         LAUNCHCHK(S);
-        long long left = nsteps;
-        if (left >= S->graph_cycle) {
-            hipGraphExec_t ex = nullptr;
-            gpr_status rc = plain_graph(S, nrep, code, &ex);
-            if (rc) return rc;
-            for (; left >= S->graph_cycle; left -= S->graph_cycle) HIPCHK(S, hipGraphLaunch(ex, S->stream));
-        }
-        for (; left > 0; --left) {
-            gpr_status rc = launch_step_dc(S, nrep, code, S->stream);
-            if (rc) return rc;
-        }
-        S->s += nsteps;
-        if (state_end) {
-            hipLaunchKernelGGL(k_state, dim3(nrep), dim3(256), S->lds_stage, S->stream, S->d_dev, 0);
-            LAUNCHCHK(S);
-        }
-        return GPR_OK;
-    }
-    const int BTI = 256;
-    dim3 gi((S->n + BTI - 1) / BTI, nrep);
-    for (long long k = 0; k < nsteps; ++k) {
-        const long long tl = t0 + k + 1;
-        const bool samp = sample && nrep > 1 && (tl % S->t_gr == 0);
-        const int energy = (samp && S->d.need_energy) ? 1 : 0;
-        hipLaunchKernelGGL(k_integrate, gi, dim3(BTI), 0, S->stream, S->d_dev, S->s, 0, energy);
-        LAUNCHCHK(S);
-        gpr_status rc = launch_forces(S, 0, nrep, S->s, energy, 1, 0, true);
-        if (rc) return rc;
-        S->s += 1;
-        if (samp) {
-            hipLaunchKernelGGL(k_obs, dim3(nrep - 1), dim3(256), S->lds_stage, S->stream, S->d_dev, 1, 0, nullptr);
-            LAUNCHCHK(S);
+        for (; left >= S->graph_cycle; left -= S->graph_cycle) {
+            HIPCHK(S, hipGraphLaunch(ex, S->stream));
+            S->s += S->graph_cycle;
+            tcur += S->graph_cycle;
         }
     }
+    gpr_status rc = plain_steps(S, nrep, left, tcur, sample);
+    if (rc) return rc;
     if (state_end) {
         hipLaunchKernelGGL(k_state, dim3(nrep), dim3(256), S->lds_stage, S->stream, S->d_dev, 0);
         LAUNCHCHK(S);
@@ -919,7 +932,7 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
     HIPCHK(S, hipMemsetAsync(d.need_build, 0, sizeof(int) * R, S->stream));
     rc = launch_forces(S, 0, R, -1, 1, 0, 1);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_obs, dim3(1), dim3(256), S->lds_stage, S->stream, S->d_dev, 0, 1, nullptr);
+    hipLaunchKernelGGL(k_obs, dim3(1), dim3(256), S->lds_stage, S->stream, S->d_dev, 0, 1, nullptr, 0);
     LAUNCHCHK(S);
     rc = state_of_ref(S, &S->omega);
     if (rc) return rc;
@@ -1346,7 +1359,7 @@ extern "C" gpr_status gpr_observe(gpr_system *S, double *obs, int32_t *state)
         gpr_status rc = launch_forces(S, 0, S->R, -1, 1, 0, 1);
         if (rc) return rc;
     }
-    hipLaunchKernelGGL(k_obs, dim3(S->R), dim3(256), S->lds_stage, S->stream, S->d_dev, 0, 2, S->obs_out);
+    hipLaunchKernelGGL(k_obs, dim3(S->R), dim3(256), S->lds_stage, S->stream, S->d_dev, 0, 2, S->obs_out, 0);
     LAUNCHCHK(S);
     hipLaunchKernelGGL(k_state, dim3(S->R), dim3(256), S->lds_stage, S->stream, S->d_dev, 0);
     LAUNCHCHK(S);
@@ -1423,7 +1436,7 @@ extern "C" gpr_status gpr_dephase(gpr_system *S, int64_t max_steps, gpr_dephase_
             rc = launch_forces(S, 0, 1, -1, 1, 0, 1);
             if (rc) return rc;
         }
-        hipLaunchKernelGGL(k_obs, dim3(1), dim3(256), S->lds_stage, S->stream, S->d_dev, 0, 1, nullptr);
+        hipLaunchKernelGGL(k_obs, dim3(1), dim3(256), S->lds_stage, S->stream, S->d_dev, 0, 1, nullptr, 0);
         LAUNCHCHK(S);
         S->nsamp = 0;
         S->dp_t = 0;

@@ -26,11 +26,11 @@ struct Split {
 };
 
 __global__ void k_set_clock(const Dev *__restrict__ Sp, long long s, long long t);
-__global__ void k_tick(const Dev *__restrict__ Sp);
+__global__ void k_tick(const Dev *__restrict__ Sp, long long n);
 __global__ void k_integrate(const Dev *__restrict__ Sp, long long s, int r_off, int energy);
-__global__ void k_bonded(const Dev *__restrict__ Sp, int r_off, int energy);
+__global__ void k_bonded(const Dev *__restrict__ Sp, long long s, int r_off, int energy);
 __global__ void k_nonbonded(const Dev *__restrict__ Sp, long long s, int r_off, int energy, int apply_b, int force_build);
-__global__ void k_obs(const Dev *__restrict__ Sp, int r_off, int mode, double *out);
+__global__ void k_obs(const Dev *__restrict__ Sp, int r_off, int mode, double *out, int k);
 __global__ void k_state(const Dev *__restrict__ Sp, int r_off);
 // one system's share of a persistent launch (see k_persist)
 struct PersistItem {

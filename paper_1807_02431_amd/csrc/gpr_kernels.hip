@@ -628,13 +628,15 @@ __device__ __forceinline__ void stage_replica(const Dev &S, int r, float4 *xs, f
 }
 
 // ================================================================== plain path kernels
-// Step and energy flag of a plain-path kernel: as given, or from the device clock (codes
-// DCLK_*), where a step samples when (t + 1) is a multiple of t_GR.
+// Step and energy flag of a plain-path kernel: as given, or (codes DCLK_*) step k of a cycle
+// that starts at the device clock (s, t) = (clock[0], clock[1]), with k passed in s; such a
+// step samples when (t + k + 1) is a multiple of t_GR.
 __device__ __forceinline__ void step_args(const Dev &S, long long &s, int &energy)
 {
     if (energy < DCLK_SAMPLE) return;
-    const bool samp = energy == DCLK_SAMPLE && (S.clock[1] + 1) % S.t_gr == 0;
-    s = S.clock[0];
+    const long long k = s;
+    const bool samp = energy == DCLK_SAMPLE && (S.clock[1] + k + 1) % S.t_gr == 0;
+    s = S.clock[0] + k;
     energy = (samp && S.need_energy) ? 1 : 0;
 }
 
@@ -644,10 +646,10 @@ __global__ void k_set_clock(const Dev *__restrict__ Sp, long long s, long long t
     Sp->clock[1] = t;
 }
 
-__global__ void k_tick(const Dev *__restrict__ Sp)
+__global__ void k_tick(const Dev *__restrict__ Sp, long long n)
 {
-    Sp->clock[0] += 1;
-    Sp->clock[1] += 1;
+    Sp->clock[0] += n;
+    Sp->clock[1] += n;
 }
 // B A O A for every atom of replicas r_off + blockIdx.y; displacement guard; energy reset.
 __global__ void __launch_bounds__(256) k_integrate(const Dev *__restrict__ Sp, long long s, int r_off, int energy)
@@ -683,11 +685,10 @@ __global__ void __launch_bounds__(256) k_integrate(const Dev *__restrict__ Sp, l
 
 // Bonded forces of atom range [blockIdx.x * blockDim.x, +blockDim.x) of replica r:
 // fixed-point LDS accumulation, then a plain store that initialises F for the step.
-__global__ void __launch_bounds__(256) k_bonded(const Dev *__restrict__ Sp, int r_off, int energy)
+__global__ void __launch_bounds__(256) k_bonded(const Dev *__restrict__ Sp, long long s, int r_off, int energy)
 {
     const Dev &S = *Sp;
-    long long s_unused = 0;
-    step_args(S, s_unused, energy);
+    step_args(S, s, energy);
     extern __shared__ __align__(16) unsigned char lds_raw[];
     long long *fa = (long long *)lds_raw;
     __shared__ long long e_acc;
@@ -808,10 +809,10 @@ __global__ void __launch_bounds__(1024) k_nonbonded(const Dev *__restrict__ Sp, 
 
 // observables of replicas r_off + blockIdx.x: accumulate (mode 0, workers), set the shift
 // c_j from replica 0 (mode 1), or write the values to out[r][MAX_OBS] (mode 2)
-__global__ void __launch_bounds__(256) k_obs(const Dev *__restrict__ Sp, int r_off, int mode, double *out)
+__global__ void __launch_bounds__(256) k_obs(const Dev *__restrict__ Sp, int r_off, int mode, double *out, int k)
 {
     const Dev &S = *Sp;
-    if (mode == 3 && (S.clock[1] + 1) % S.t_gr != 0) return;    // device clock: not a sampling step
+    if (mode == 3 && (S.clock[1] + k + 1) % S.t_gr != 0) return;    // step k of a device-clock cycle: no sample
     extern __shared__ __align__(16) unsigned char lds_raw[];
     float4 *xs = (float4 *)lds_raw;
     __shared__ long long red[MAX_OBS * 8 + 8];
