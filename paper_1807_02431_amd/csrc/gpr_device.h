@@ -32,7 +32,8 @@ constexpr int BLK = 8;          // consecutive atoms per bounding sphere in the 
 constexpr int WBLK = 64;        // LDS ints per wave: the near blocks of one 64-block chunk in the pair search
 constexpr double FIX = 4294967296.0;          // 2^32
 constexpr double FIX_INV = 2.3283064365386963e-10;  // 2^-32
-constexpr float FMAX_FIX = 1.0e9f;             // |F| beyond this counts as unstable
+constexpr float FMAX_FIX = 2.5e5f;             // |F| beyond this (kJ/mol/nm) counts as unstable
+constexpr float FSAT = 524287.0f;              // 2^19 - 1: fixed-point conversions saturate here
 constexpr float FAR = 1.0e15f;                 // coordinate of the dummy atom
 constexpr int SPIN_MAX = 1 << 22;              // bound on a barrier wait (then ERR_BARRIER)
 // energy codes of the plain-path kernels: 0 / 1 given by the host; DCLK_* take the step s and
@@ -190,7 +191,16 @@ __device__ __forceinline__ float3 gauss3(uint4 w)
 }
 
 // ------------------------------------------------------------------ fixed point
-__device__ __forceinline__ long long fix_f(float f) { return __double2ll_rn((double)f * FIX); }
+// f 2^32 rounded to the nearest integer (ties to even) as a 64-bit integer.  In FP64 the sum
+// f 2^32 + 1.5 2^52 lies in [2^52, 2^53), where the spacing is 1, so one rounding leaves the
+// integer in the low bits of the mantissa: exact while |f| < 2^19.  Larger values (and NaN)
+// saturate at +-FSAT, which the FMAX_FIX test on the summed force reports as unstable.
+__device__ __forceinline__ long long fix_f(float f)
+{
+    const float c = fminf(fmaxf(f, -FSAT), FSAT);
+    const double y = __builtin_fma((double)c, FIX, 6755399441055744.0);
+    return __double_as_longlong(y) - 0x4338000000000000LL;
+}
 __device__ __forceinline__ long long fix_d(double d) { return __double2ll_rn(d * FIX); }
 __device__ __forceinline__ float unfix_f(long long a) { return (float)((double)a * FIX_INV); }
 __device__ __forceinline__ double unfix_d(long long a) { return (double)a * FIX_INV; }

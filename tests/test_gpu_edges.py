@@ -140,3 +140,22 @@ def test_every_worker_exits_at_a_check(path, seed):
         assert s.accumulators()[0] == 0
     assert np.abs(g.get_state(0)[0] - o.get_state(0)[0]).max() < 1e-5
     assert g.simulated_steps() == o.simulated_steps()
+
+
+@pytest.mark.parametrize("path", [0, 1])
+def test_overlapping_atoms_are_reported_unstable(path):
+    """Two non-bonded atoms placed 0.001 nm apart (forced from the host with gpr_set_state): the
+    Lennard-Jones force, far beyond any stable value, is reported as GPR_EUNSTABLE by the next
+    call that steps, on both paths; the other replica stays finite."""
+    gpr = _gpr()
+    spec = G.config("rl300", n_replicas=2)
+    say("overlap, path", path)
+    g = gpr.System(spec, path=path)
+    q0, _ = g.get_state(0)
+    q, v = g.get_state(1)
+    q[:, 10] = q[:, 200] + np.array([1e-3, 0.0, 0.0])
+    g.set_state(1, q, v)
+    with pytest.raises(gpr.GprError) as e:
+        g.advance(20)
+    assert e.value.code == -5
+    assert np.isfinite(g.get_state(0)[0]).all()
