@@ -250,9 +250,11 @@ __device__ __forceinline__ float wave16_max(float v)
 // with the dummy atom n.  allpairs: no distance tests (vacuum, no cutoff; r_list^2 = inf).
 // Per 64-block chunk the near blocks are listed in the wave's LDS scratch wblk (ascending);
 // their candidates are tested without branches, the outcomes kept as bits (BLK / P per block,
-// 32 blocks per batch), and each lane then writes the entries it keeps, dropping itself and
-// excluded partners at that point.  UNR blocks are read at a time (more registers, fewer
-// exposed LDS latencies); the plain path's pair kernel uses 1 to keep its occupancy.
+// 32 blocks per batch), and each lane then writes the entries it keeps.  Itself and excluded
+// partners (all within 32 atoms of it) are dropped in the tests, only for blocks near the
+// wave's own atoms; atoms past n are staged far away, so the distance test drops them.  UNR
+// blocks are read at a time (more registers, fewer exposed LDS latencies); the plain path's
+// pair kernel uses 1 to keep its occupancy.
 template <int UNR>
 __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool valid, const GPR_LDS gv_f4 *xs,
                                        const GPR_LDS gv_f4 *sph, GPR_LDS int *wblk, bool allpairs)
@@ -273,7 +275,10 @@ __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool v
         d2 = dx * dx + dy * dy + dz * dz;
     }
     const float rw = S.rl + sqrtf(wave16_max(d2)) * 1.0001f + 1e-6f;
-    const float rl2 = S.rl2;
+    // finite even without a cutoff, so that the far-away atoms past n never pass
+    const float rl2 = fminf(S.rl2, 1.0e30f);
+    // atoms [iw, iw + 16) of the wave (lane 0 holds the first)
+    const int iw = __builtin_amdgcn_readfirstlane(i);
     // partners to drop: excluded and 1-4 pairs within +-32 of i, and i itself (bit 32)
     const unsigned long long ex = (valid ? gconst(S.excl)[i] : 0ull) | (1ull << 32);
     const int cap = 4 * S.Kg;
@@ -290,31 +295,38 @@ __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool v
     // group cnt / 4, and a group is stored once complete
     auto emit = [&](int base) {
         __builtin_amdgcn_wave_barrier();
-        while (bits) {
-            int k[UNR], bk[UNR];
+        // two halves of 16 blocks (32 bits) each, entries in ascending order
 #pragma unroll
-            for (int e = 0; e < UNR; ++e) {
-                k[e] = bits ? __builtin_ctzll(bits) : -1;
-                bits &= bits - 1ull;
-            }
+        for (int h = 0; h < 2; ++h) {
+            unsigned b32 = h ? (unsigned)(bits >> 32) : (unsigned)bits;
+            const int hb = base + 16 * h;
+            while (b32) {
+                int k[UNR], bk[UNR];
+                bool has[UNR];
 #pragma unroll
-            for (int e = 0; e < UNR; ++e) bk[e] = wblk[base + (k[e] >= 0 ? k[e] / CPB : 0)];
-#pragma unroll
-            for (int e = 0; e < UNR; ++e) {
-                if (k[e] < 0) break;
-                const int j = bk[e] * BLK + q + (k[e] % CPB) * P;
-                const int off = j - i + 32;
-                if ((unsigned)off < 64u && ((ex >> off) & 1ull)) continue;
-                if (cnt < cap) {
-                    word |= (unsigned long long)j << (16 * (cnt & 3));
-                    if ((cnt & 3) == 3) {
-                        gst(L + (size_t)(cnt >> 2) * stride, word);
-                        word = 0ull;
-                    }
+                for (int e = 0; e < UNR; ++e) {
+                    has[e] = b32 != 0u;
+                    k[e] = __builtin_ctz(b32 | (has[e] ? 0u : 1u));
+                    b32 &= b32 - 1u;
                 }
-                ++cnt;
+#pragma unroll
+                for (int e = 0; e < UNR; ++e) bk[e] = wblk[hb + k[e] / CPB];
+#pragma unroll
+                for (int e = 0; e < UNR; ++e) {
+                    if (!has[e]) continue;
+                    const int j = bk[e] * BLK + q + (k[e] % CPB) * P;
+                    if (cnt < cap) {
+                        word |= (unsigned long long)j << (16 * (cnt & 3));
+                        if ((cnt & 3) == 3) {
+                            gst(L + (size_t)(cnt >> 2) * stride, word);
+                            word = 0ull;
+                        }
+                    }
+                    ++cnt;
+                }
             }
         }
+        bits = 0ull;
         __builtin_amdgcn_wave_barrier();
     };
     for (int cb = 0; cb < nblk; cb += 64) {
@@ -348,9 +360,9 @@ __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool v
             for (int u = 0; u < UNR; ++u)
 #pragma unroll
                 for (int t = 0; t < CPB; ++t)
-                    pj[u][t] = x3[bbs[u] >= 0 ? min(bbs[u] * BLK + q + t * P, n) : n];
+                    pj[u][t] = x3[bbs[u] >= 0 ? bbs[u] * BLK + q + t * P : n];
             __builtin_amdgcn_sched_barrier(0);                  // keep the reads ahead of the tests
-            unsigned long long tb = 0ull;
+            unsigned tb = 0u;
 #pragma unroll
             for (int u = 0; u < UNR; ++u)
 #pragma unroll
@@ -358,11 +370,25 @@ __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool v
                     const float dx = pi.x - pj[u][t].x, dy = pi.y - pj[u][t].y, dz = pi.z - pj[u][t].z;
                     // bitwise, not short-circuit, so that no branch is generated
                     const unsigned take = (unsigned)valid & (unsigned)(bbs[u] >= 0) &
-                                          (unsigned)(bbs[u] * BLK + q + t * P < n) &
                                           (unsigned)(fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < rl2);
-                    tb |= (unsigned long long)take << (u * CPB + t);
+                    tb |= take << (u * CPB + t);
                 }
-            bits |= tb << (((k0 - base) % BATCH) * CPB);
+            // blocks that may hold the wave's atoms or their excluded partners (wave-uniform)
+            bool self = false;
+#pragma unroll
+            for (int u = 0; u < UNR; ++u)
+                self |= bbs[u] >= 0 && bbs[u] * BLK + BLK > iw - 32 && bbs[u] * BLK < iw + 16 + 32;
+            if (self) {
+#pragma unroll
+                for (int u = 0; u < UNR; ++u)
+#pragma unroll
+                    for (int t = 0; t < CPB; ++t) {
+                        const int off = bbs[u] * BLK + q + t * P - i + 32;
+                        const unsigned drop = (unsigned)((unsigned)off < 64u) & (unsigned)((ex >> (off & 63)) & 1ull);
+                        tb &= ~(drop << (u * CPB + t));
+                    }
+            }
+            bits |= (unsigned long long)tb << (((k0 - base) % BATCH) * CPB);
             if (k0 + UNR - base == BATCH) {
                 emit(base);
                 base += BATCH;
