@@ -362,17 +362,17 @@ __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool v
                 for (int t = 0; t < CPB; ++t)
                     pj[u][t] = x3[bbs[u] >= 0 ? bbs[u] * BLK + q + t * P : n];
             __builtin_amdgcn_sched_barrier(0);                  // keep the reads ahead of the tests
+            // a missing block reads the far-away atom n, which fails the distance test; a lane
+            // without an atom (its position also the far-away one) keeps no bit
             unsigned tb = 0u;
 #pragma unroll
             for (int u = 0; u < UNR; ++u)
 #pragma unroll
                 for (int t = 0; t < CPB; ++t) {
                     const float dx = pi.x - pj[u][t].x, dy = pi.y - pj[u][t].y, dz = pi.z - pj[u][t].z;
-                    // bitwise, not short-circuit, so that no branch is generated
-                    const unsigned take = (unsigned)valid & (unsigned)(bbs[u] >= 0) &
-                                          (unsigned)(fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < rl2);
-                    tb |= take << (u * CPB + t);
+                    tb |= (unsigned)(fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < rl2) << (u * CPB + t);
                 }
+            tb = valid ? tb : 0u;
             // blocks that may hold the wave's atoms or their excluded partners (wave-uniform)
             bool self = false;
 #pragma unroll
@@ -449,11 +449,12 @@ __device__ __forceinline__ float4 nb_lane_t(const Dev &S, int r, int i, int q, c
     const float2 ppi = pp[i];
     const float rc2 = S.rc2, krf = S.krf, krf2 = 2.0f * S.krf, crf = S.crf;
     float fx = 0.f, fy = 0.f, fz = 0.f, e = 0.f;
+    // the next word is read one group ahead, without a branch (the last group re-reads itself)
     uint2 nxt = make_uint2(0u, 0u);
     if (ng > 0) nxt = gld(L);
     for (int g = 0; g < ng; ++g) {
         const uint2 cur = nxt;
-        if (g + 1 < ng) nxt = gld(L + (size_t)(g + 1) * stride);
+        nxt = gld(L + (size_t)min(g + 1, ng - 1) * stride);
         const int j0 = cur.x & 0xFFFF, j1 = cur.x >> 16, j2 = cur.y & 0xFFFF, j3 = cur.y >> 16;
         const float4 x0 = xs[j0], x1 = xs[j1], x2 = xs[j2], x3 = xs[j3];
         const float2 p0 = pp[j0], p1 = pp[j1], p2 = pp[j2], p3 = pp[j3];
