@@ -94,7 +94,8 @@ template <class Pos>
 __device__ void bonded_range(const Dev &S, const BondedPlan &bp, const Pos &pos, int a0, int a1, long long *fa,
                              int len, long long *e_acc, int tid, int nthr)
 {
-    const Topo &T = S.tp;
+    // the topology's pointers, read once per call (not again after each LDS atomic)
+    const Topo T = S.tp;
     auto add = [&](int a, float3 f) {
         if (a >= a0 && a < a1) {
             lds_add(&fa[a - a0], fix_f(f.x));
@@ -437,10 +438,24 @@ __device__ __forceinline__ void pair_term(const float4 pi, const float2 ppi, con
     }
 }
 
+// The pair loop's parameters, as values (read once per step in a persistent launch)
+struct NbConsts {
+    const uint2 *nbl;
+    const unsigned short *nbc;
+    int np, Kg;
+    float rc2, krf, crf;
+};
+__device__ __forceinline__ NbConsts nb_consts(const Dev &S)
+{
+    NbConsts k;
+    k.nbl = S.nbl; k.nbc = S.nbc; k.np = S.np; k.Kg = S.Kg; k.rc2 = S.rc2; k.krf = S.krf; k.crf = S.crf;
+    return k;
+}
+
 // Sum over sub-list (i, q), four partners per 8-byte list word, the next word loaded one
 // group ahead; returns (F_x, F_y, F_z, sum U/2).
 template <bool ENERGY>
-__device__ __forceinline__ float4 nb_lane_t(const Dev &S, int r, int i, int q, const float4 *xs, const float2 *pp)
+__device__ __forceinline__ float4 nb_lane_t(const NbConsts &S, int r, int i, int q, const float4 *xs, const float2 *pp)
 {
     const size_t stride = (size_t)S.np * P;
     const GPR_GLOBAL uint2 *L = gconst(S.nbl) + (size_t)r * S.Kg * stride + (size_t)i * P + q;
@@ -466,30 +481,50 @@ __device__ __forceinline__ float4 nb_lane_t(const Dev &S, int r, int i, int q, c
     return make_float4(fx, fy, fz, e);
 }
 
-__device__ __forceinline__ float4 nb_lane(const Dev &S, int r, int i, int q, const float4 *xs, const float2 *pp,
+__device__ __forceinline__ float4 nb_lane(const NbConsts &S, int r, int i, int q, const float4 *xs, const float2 *pp,
                                           bool energy)
 {
     return energy ? nb_lane_t<true>(S, r, i, q, xs, pp) : nb_lane_t<false>(S, r, i, q, xs, pp);
 }
 
 // ------------------------------------------------------------------ one B A O A for one atom
-__device__ __forceinline__ void integrate_baoa(const Dev &S, int a, int r, long long s, float3 &x, float3 &v,
-                                               float3 F, float im, float sd)
+// The integrator's constants, as values: a persistent launch holds them in registers (read
+// through the descriptor they would be loaded again after every fence of a step).
+struct IntConsts {
+    float h, c1;
+    uint32_t key0, key1;
+    int toy;
+};
+__device__ __forceinline__ IntConsts int_consts(const Dev &S)
 {
-    const float h = S.h, c1 = S.c1;
+    IntConsts k;
+    k.h = S.h; k.c1 = S.c1; k.key0 = S.key0; k.key1 = S.key1; k.toy = S.kind == KIND_TOY;
+    return k;
+}
+
+__device__ __forceinline__ void integrate_baoa_k(const IntConsts &K, int a, int r, long long s, float3 &x, float3 &v,
+                                                 float3 F, float im, float sd)
+{
+    const float h = K.h, c1 = K.c1;
     v.x = kick(v.x, F.x, h, im);
     v.y = kick(v.y, F.y, h, im);
     v.z = kick(v.z, F.z, h, im);
     x.x = x.x + h * v.x;
     x.y = x.y + h * v.y;
     x.z = x.z + h * v.z;
-    const float3 g = gauss3(philox_ctr((uint32_t)a, s, (uint32_t)r, STREAM_NOISE, S.key0, S.key1));
+    const float3 g = gauss3(philox_ctr((uint32_t)a, s, (uint32_t)r, STREAM_NOISE, K.key0, K.key1));
     v.x = c1 * v.x + sd * g.x;
     v.y = c1 * v.y + sd * g.y;
-    if (S.kind != KIND_TOY) v.z = c1 * v.z + sd * g.z;
+    if (!K.toy) v.z = c1 * v.z + sd * g.z;
     x.x = x.x + h * v.x;
     x.y = x.y + h * v.y;
     x.z = x.z + h * v.z;
+}
+
+__device__ __forceinline__ void integrate_baoa(const Dev &S, int a, int r, long long s, float3 &x, float3 &v,
+                                               float3 F, float im, float sd)
+{
+    integrate_baoa_k(int_consts(S), a, r, s, x, v, F, im, sd);
 }
 
 __device__ __forceinline__ bool finite3(float3 a) { return isfinite(a.x) && isfinite(a.y) && isfinite(a.z); }
@@ -803,7 +838,7 @@ __global__ void __launch_bounds__(1024) k_nonbonded(const Dev *__restrict__ Sp, 
     }
     long long eatom = 0;
     if (i < S.n) {
-        float4 f = nb_lane(S, r, i, q, xs, pp, energy != 0);
+        float4 f = nb_lane(nb_consts(S), r, i, q, xs, pp, energy != 0);
         f.x = quad_sum(f.x);
         f.y = quad_sum(f.y);
         f.z = quad_sum(f.z);
@@ -1147,6 +1182,11 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
     __syncthreads();
     const bool toy = S.kind == KIND_TOY;
     const int nl = a1 - a0, nslot = 16 * ((nl + 15) >> 4);
+    // descriptor fields used every step, held in registers for the launch
+    const IntConsts ik = int_consts(S);
+    const int t_gr = S.t_gr, need_energy = S.need_energy, cutoff_on = S.cutoff_on, period = S.period;
+    const float half_skin2 = S.half_skin2;
+    int *const errp = S.err;
     if (!toy) {
         // the lists in place (built by an earlier launch) give the first order
         const GPR_GLOBAL unsigned short *cg = gconst(S.nbc) + (size_t)r * np * P + (size_t)a0 * P;
@@ -1168,8 +1208,8 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
     for (int step = 0; step < nsteps && alive; ++step) {
         const long long s = s0 + step;
         const int tl = t0 + step + 1;
-        const bool samp = sample && r >= 1 && (tl % S.t_gr == 0);
-        const bool energy = samp && S.need_energy;
+        const bool samp = sample && r >= 1 && (tl % t_gr == 0);
+        const bool energy = samp && need_energy;
         unsigned long long *xch_xy = xch_xy0 + (s & 1) * np;
         float *xch_z = xch_z0 + (s & 1) * np;
         int hit = 0, bad = 0;
@@ -1178,17 +1218,17 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
             float3 x = make_float3(xs[a].x, xs[a].y, xs[a].z);
             float3 v = make_float3(vs[l], vs[lmax + l], vs[2 * lmax + l]);
             const float3 F = make_float3(unfix_f(fa[l]), unfix_f(fa[lmax + l]), unfix_f(fa[2 * lmax + l]));
-            integrate_baoa(S, a, r, s, x, v, F, iml[l], sdl[l]);
+            integrate_baoa_k(ik, a, r, s, x, v, F, iml[l], sdl[l]);
             xs[a].x = x.x; xs[a].y = x.y; xs[a].z = x.z;
             vs[l] = v.x; vs[lmax + l] = v.y; vs[2 * lmax + l] = v.z;
             if (G > 1) { st_coh2(xch_xy + a, x.x, x.y); st_coh(xch_z + a, x.z); }
             bad |= !(finite3(x) && finite3(v));
-            if (S.cutoff_on) {
+            if (cutoff_on) {
                 const float dx = x.x - xbl[l], dy = x.y - xbl[lmax + l], dz = x.z - xbl[2 * lmax + l];
-                hit |= !(dx * dx + dy * dy + dz * dz <= S.half_skin2);
+                hit |= !(dx * dx + dy * dy + dz * dz <= half_skin2);
             }
         }
-        if (bad) atomicOr(&S.err[ERR_UNSTABLE], 1);
+        if (bad) atomicOr(&errp[ERR_UNSTABLE], 1);
         int any_hit;
         if (G > 1) {
             // displacement-guard flags in three rotating slots; group 0 clears the slot of the next step
@@ -1212,7 +1252,7 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
                         int spins = 0;
                         while (__hip_atomic_load(sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
                             if (++spins > SPIN_MAX) {
-                                atomicOr(S.err + ERR_BARRIER, 1);
+                                atomicOr(errp + ERR_BARRIER, 1);
                                 bbuf = 0;
                                 break;
                             }
@@ -1246,7 +1286,7 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
                 alive = bbuf != 0;
                 if (!alive) break;
             } else {
-                alive = group_barrier(sync, G * ++gen, S.err, &bbuf);
+                alive = group_barrier(sync, G * ++gen, errp, &bbuf);
                 if (!alive) break;
                 if (tid == 0) hbuf = __hip_atomic_load(sync + 16 + 16 * (int)(s % 3), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 for (int a = tid; a < n; a += BT) {
@@ -1262,7 +1302,7 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
         }
         // each replica is its own set of workgroups here, so its list is rebuilt when it is
         // period steps old (or flagged), independently of the other replicas
-        if (S.cutoff_on && (need || any_hit || s - lastb >= S.period)) {
+        if (cutoff_on && (need || any_hit || s - lastb >= period)) {
             lastb = s;
             block_spheres(S, xs, sph, tid, BT);
             __syncthreads();
@@ -1302,6 +1342,7 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
             // the waves take from a shared counter as they come free
             bonded_range(S, bplan, PosLDS{xs}, a0, a1, fa, lmax, energy ? eacc : nullptr, tid, BT);
             const int ntask = nslot >> 4;
+            const NbConsts nbk = nb_consts(S);
             for (;;) {
                 int t = 0;
                 if ((tid & 63) == 0) t = atomicAdd(&ptask, 1);
@@ -1312,7 +1353,7 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
                 long long eatom = 0;
                 if (l != 0xFFFF) {
                     const int i = a0 + l;
-                    float4 f = nb_lane(S, r, i, q, xs, pp, energy);
+                    float4 f = nb_lane(nbk, r, i, q, xs, pp, energy);
                     f.x = quad_sum(f.x);
                     f.y = quad_sum(f.y);
                     f.z = quad_sum(f.z);
@@ -1333,12 +1374,12 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
         __syncthreads();
         for (int a = a0 + tid; a < a1; a += BT) {
             const int l = a - a0;
-            const float im = iml[l], h = S.h;
+            const float im = iml[l], h = ik.h;
             const float Fx = unfix_f(fa[l]), Fy = unfix_f(fa[lmax + l]), Fz = unfix_f(fa[2 * lmax + l]);
             vs[l] = kick(vs[l], Fx, h, im);
             vs[lmax + l] = kick(vs[lmax + l], Fy, h, im);
             vs[2 * lmax + l] = kick(vs[2 * lmax + l], Fz, h, im);
-            if (bad_force(Fx) || bad_force(Fy) || bad_force(Fz)) atomicOr(&S.err[ERR_UNSTABLE], 1);
+            if (bad_force(Fx) || bad_force(Fy) || bad_force(Fz)) atomicOr(&errp[ERR_UNSTABLE], 1);
         }
         if (samp) {
             __syncthreads();
