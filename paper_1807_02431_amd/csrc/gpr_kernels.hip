@@ -90,7 +90,7 @@ __device__ __forceinline__ BondedPlan bonded_plan(const Dev &S, int a0, int a1, 
 // fa[3][len] (LDS, index a - a0); the energy of a term is counted by the range holding its
 // smallest atom.  Each thread takes up to four slots at a time and issues all their topology
 // loads before computing any of them.  nthr must be a multiple of 64.
-template <class Pos>
+template <class Pos, int U = 4>
 __device__ void bonded_range(const Dev &S, const BondedPlan &bp, const Pos &pos, int a0, int a1, long long *fa,
                              int len, long long *e_acc, int tid, int nthr)
 {
@@ -103,7 +103,6 @@ __device__ void bonded_range(const Dev &S, const BondedPlan &bp, const Pos &pos,
             lds_add(&fa[2 * len + a - a0], fix_f(f.z));
         }
     };
-    constexpr int U = 4;
     long long e = 0;
     const int total = bp.off[5];
     for (int base = 0; base < total; base += U * nthr) {
@@ -1280,7 +1279,7 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
                         }
                     }
                 } else {
-                    bonded_range(S, bpin, PosLDS{xs}, a0, a1, fa, lmax, energy ? eacc : nullptr, tid - XT, BT - XT);
+                    bonded_range<PosLDS, 2>(S, bpin, PosLDS{xs}, a0, a1, fa, lmax, energy ? eacc : nullptr, tid - XT, BT - XT);
                 }
                 __syncthreads();
                 alive = bbuf != 0;
@@ -1340,7 +1339,7 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
         } else {
             // bonded terms, then the pair loop, whose tasks (16 atoms each, longest lists first)
             // the waves take from a shared counter as they come free
-            bonded_range(S, bplan, PosLDS{xs}, a0, a1, fa, lmax, energy ? eacc : nullptr, tid, BT);
+            bonded_range<PosLDS, 2>(S, bplan, PosLDS{xs}, a0, a1, fa, lmax, energy ? eacc : nullptr, tid, BT);
             const int ntask = nslot >> 4;
             const NbConsts nbk = nb_consts(S);
             for (;;) {
