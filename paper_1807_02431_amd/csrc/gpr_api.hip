@@ -229,7 +229,7 @@ static size_t persist_lds(int n, int np, const Split &sp)
     const int nblk = (n + BLK - 1) / BLK;
     return (size_t)3 * lmax * 8 + (MAX_OBS * 8 + 8) * 8 + MAX_OBS * 8 + (size_t)np * 16 + (size_t)np * 8 +
            (size_t)8 * lmax * 4 + (size_t)nblk * 16 + (size_t)16 * WBLK * 4 + (size_t)32 * ((lmax + 15) / 16) +
-           (size_t)lmax;
+           (size_t)2 * lmax;
 }
 
 // ------------------------------------------------------------------ force-field parameters

@@ -397,14 +397,20 @@ __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool v
         emit(base);
     }
     if (!valid) return 0;
-    const int ng = (cnt + 3) >> 2;
+    const int ng = min((cnt + 3) >> 2, S.Kg);
     if ((cnt & 3) != 0 && cnt < cap) {
         for (int k = cnt & 3; k < 4; ++k) word |= (unsigned long long)n << (16 * k);
         gst(L + (size_t)(cnt >> 2) * stride, word);
     }
-    gmut(S.nbc)[(size_t)r * stride + (size_t)i * P + q] = (unsigned short)min(ng, S.Kg);
+    // the four sub-lists of an atom padded to the same number of groups with the far-away
+    // atom n (exact zeros), so that one count serves the atom's four lanes
+    int kq = max(ng, __shfl_xor(ng, 1, 64));
+    kq = max(kq, __shfl_xor(kq, 2, 64));
+    const unsigned long long pad = (unsigned long long)n * 0x0001000100010001ull;
+    for (int w = ng; w < kq; ++w) gst(L + (size_t)w * stride, pad);
+    gmut(S.nbc)[(size_t)r * stride + (size_t)i * P + q] = (unsigned short)kq;
     if (cnt > cap) atomicOr(&S.err[ERR_LIST], 1);
-    return min(ng, S.Kg);
+    return kq;
 }
 
 // ------------------------------------------------------------------ nonbonded partial sum of one lane
@@ -454,11 +460,13 @@ __device__ __forceinline__ NbConsts nb_consts(const Dev &S)
 // Sum over sub-list (i, q), four partners per 8-byte list word, the next word loaded one
 // group ahead; returns (F_x, F_y, F_z, sum U/2).
 template <bool ENERGY>
-__device__ __forceinline__ float4 nb_lane_t(const NbConsts &S, int r, int i, int q, const float4 *xs, const float2 *pp)
+__device__ __forceinline__ float4 nb_lane_t(const NbConsts &S, int r, int i, int q, const float4 *xs, const float2 *pp,
+                                            int ngk)
 {
     const size_t stride = (size_t)S.np * P;
     const GPR_GLOBAL uint2 *L = gconst(S.nbl) + (size_t)r * S.Kg * stride + (size_t)i * P + q;
-    const int ng = gconst(S.nbc)[(size_t)r * stride + (size_t)i * P + q];
+    // groups in the sub-list: given (the atom's count kept in LDS), or read from the counts
+    const int ng = ngk >= 0 ? ngk : (int)gconst(S.nbc)[(size_t)r * stride + (size_t)i * P + q];
     const float4 pi = xs[i];
     const float2 ppi = pp[i];
     const float rc2 = S.rc2, krf = S.krf, krf2 = 2.0f * S.krf, crf = S.crf;
@@ -481,9 +489,9 @@ __device__ __forceinline__ float4 nb_lane_t(const NbConsts &S, int r, int i, int
 }
 
 __device__ __forceinline__ float4 nb_lane(const NbConsts &S, int r, int i, int q, const float4 *xs, const float2 *pp,
-                                          bool energy)
+                                          bool energy, int ngk = -1)
 {
-    return energy ? nb_lane_t<true>(S, r, i, q, xs, pp) : nb_lane_t<false>(S, r, i, q, xs, pp);
+    return energy ? nb_lane_t<true>(S, r, i, q, xs, pp, ngk) : nb_lane_t<false>(S, r, i, q, xs, pp, ngk);
 }
 
 // ------------------------------------------------------------------ one B A O A for one atom
@@ -1105,7 +1113,7 @@ __device__ __forceinline__ float2 ld_coh2(const unsigned long long *p)
 // atom's longest sub-list, in words): tasks of similar lists, taken heaviest first.  perm has
 // 16 * ceil(nl / 16) slots; those past nl hold 0xFFFF.  Forces do not depend on the order: an
 // atom's four lanes stay together and sum its own sub-lists in their fixed order.
-__device__ void order_atoms(const unsigned char *key, unsigned short *perm, int *hist, int nl, int tid, int nthr)
+__device__ void order_atoms(const unsigned short *key, unsigned short *perm, int *hist, int nl, int tid, int nthr)
 {
     const int nt = (nl + 15) >> 4;
     for (int k = tid; k < 16 * nt; k += nthr) perm[k] = 0xFFFF;
@@ -1147,7 +1155,7 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
     float4 *sph = (float4 *)(xbl + 3 * lmax);              // [nblk]
     int *wscr = (int *)(sph + (n + BLK - 1) / BLK);        // [16][WBLK] build scratch per wave
     unsigned short *perm = (unsigned short *)(wscr + 16 * WBLK);   // [16 ceil(lmax / 16)] pair-loop order
-    unsigned char *keyl = (unsigned char *)(perm + 16 * ((lmax + 15) >> 4));   // [lmax] list length, words
+    unsigned short *keyl = perm + 16 * ((lmax + 15) >> 4);  // [lmax] groups in each of an atom's sub-lists
     __shared__ int sbuf, bbuf, hbuf, hist[64], ptask;
 
     const int tid = threadIdx.x, BT = blockDim.x;
@@ -1191,7 +1199,7 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
         const GPR_GLOBAL unsigned short *cg = gconst(S.nbc) + (size_t)r * np * P + (size_t)a0 * P;
         for (int l = tid; l < nl; l += BT) {
             const int c = max(max(cg[l * P], cg[l * P + 1]), max(cg[l * P + 2], cg[l * P + 3]));
-            keyl[l] = (unsigned char)min(c, 255);
+            keyl[l] = (unsigned short)c;
         }
         order_atoms(keyl, perm, hist, nl, tid, BT);
     }
@@ -1312,12 +1320,10 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
                 const int ngw = build_wave<4>(S, r, i, q, valid, (const GPR_LDS gv_f4 *)xs,
                                               (const GPR_LDS gv_f4 *)sph, (GPR_LDS int *)wscr + (tid >> 6) * WBLK,
                                               false);
-                int kq = max(ngw, __shfl_xor(ngw, 1, 64));
-                kq = max(kq, __shfl_xor(kq, 2, 64));
                 if (valid && q == 0) {
                     const int l = i - a0;
                     xbl[l] = xs[i].x; xbl[lmax + l] = xs[i].y; xbl[2 * lmax + l] = xs[i].z;
-                    keyl[l] = (unsigned char)min(kq, 255);
+                    keyl[l] = (unsigned short)ngw;
                 }
             }
             order_atoms(keyl, perm, hist, nl, tid, BT);
@@ -1352,7 +1358,7 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
                 long long eatom = 0;
                 if (l != 0xFFFF) {
                     const int i = a0 + l;
-                    float4 f = nb_lane(nbk, r, i, q, xs, pp, energy);
+                    float4 f = nb_lane(nbk, r, i, q, xs, pp, energy, keyl[l]);
                     f.x = quad_sum(f.x);
                     f.y = quad_sum(f.y);
                     f.z = quad_sum(f.z);
