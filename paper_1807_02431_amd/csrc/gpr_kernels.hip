@@ -255,7 +255,7 @@ __device__ __forceinline__ float wave16_max(float v)
 // wave's own atoms; atoms past n are staged far away, so the distance test drops them.  UNR
 // blocks are read at a time (more registers, fewer exposed LDS latencies); the plain path's
 // pair kernel uses 1 to keep its occupancy.
-template <int UNR>
+template <int UNR, bool PAD>
 __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool valid, const GPR_LDS gv_f4 *xs,
                                        const GPR_LDS gv_f4 *sph, GPR_LDS int *wblk, bool allpairs)
 {
@@ -402,13 +402,17 @@ __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool v
         for (int k = cnt & 3; k < 4; ++k) word |= (unsigned long long)n << (16 * k);
         gst(L + (size_t)(cnt >> 2) * stride, word);
     }
-    // the four sub-lists of an atom padded to the same number of groups with the far-away
-    // atom n (exact zeros), so that one count serves the atom's four lanes
-    int kq = max(ng, __shfl_xor(ng, 1, 64));
-    kq = max(kq, __shfl_xor(kq, 2, 64));
-    const unsigned long long pad = (unsigned long long)n * 0x0001000100010001ull;
-    for (int w = ng; w < kq; ++w) gst(L + (size_t)w * stride, pad);
-    gmut(S.nbc)[(size_t)r * stride + (size_t)i * P + q] = (unsigned short)kq;
+    // PAD: the four sub-lists of an atom padded to the same number of groups with the
+    // far-away atom n (exact zeros), so that one count (the largest, returned) serves the
+    // atom's four lanes; the counts array keeps each sub-list's own count
+    int kq = ng;
+    if (PAD) {
+        kq = max(ng, __shfl_xor(ng, 1, 64));
+        kq = max(kq, __shfl_xor(kq, 2, 64));
+        const unsigned long long pad = (unsigned long long)n * 0x0001000100010001ull;
+        for (int w = ng; w < kq; ++w) gst(L + (size_t)w * stride, pad);
+    }
+    gmut(S.nbc)[(size_t)r * stride + (size_t)i * P + q] = (unsigned short)ng;
     if (cnt > cap) atomicOr(&S.err[ERR_LIST], 1);
     return kq;
 }
@@ -836,7 +840,7 @@ __global__ void __launch_bounds__(1024) k_nonbonded(const Dev *__restrict__ Sp, 
     if (rebuild) {
         block_spheres(S, xs, sph, tid, nthr);
         __syncthreads();
-        build_wave<1>(S, r, i, q, i < S.n, (const GPR_LDS gv_f4 *)xs, (const GPR_LDS gv_f4 *)sph,
+        build_wave<1, false>(S, r, i, q, i < S.n, (const GPR_LDS gv_f4 *)xs, (const GPR_LDS gv_f4 *)sph,
                    (GPR_LDS int *)wscr + (tid >> 6) * WBLK, !S.cutoff_on);
         if (i < S.n && q == 0) {
             S.xb[b + i] = xs[i].x; S.xb[b + S.np + i] = xs[i].y; S.xb[b + 2 * S.np + i] = xs[i].z;
@@ -1184,7 +1188,9 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
         iml[l] = a < a1 ? gld(prm + a).w : 0.f;
         sdl[l] = a < a1 ? sdv[a] : 0.f;
     }
-    bool need = S.need_build[r] != 0;
+    // the pair loop below runs each atom's four sub-lists to one count, which needs lists
+    // padded as this kernel's search writes them: the first step of every launch builds them
+    bool need = S.kind != KIND_TOY;
     long long lastb = S.last_build[(s0 & 1) * S.R + r];     // step of the last pair-list build
     __syncthreads();
     const bool toy = S.kind == KIND_TOY;
@@ -1194,15 +1200,6 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
     const int t_gr = S.t_gr, need_energy = S.need_energy, cutoff_on = S.cutoff_on, period = S.period;
     const float half_skin2 = S.half_skin2;
     int *const errp = S.err;
-    if (!toy) {
-        // the lists in place (built by an earlier launch) give the first order
-        const GPR_GLOBAL unsigned short *cg = gconst(S.nbc) + (size_t)r * np * P + (size_t)a0 * P;
-        for (int l = tid; l < nl; l += BT) {
-            const int c = max(max(cg[l * P], cg[l * P + 1]), max(cg[l * P + 2], cg[l * P + 3]));
-            keyl[l] = (unsigned short)c;
-        }
-        order_atoms(keyl, perm, hist, nl, tid, BT);
-    }
     // with several groups the bonded terms inside the group's range run while its first waves
     // wait at the barrier and fetch the other groups' positions; the rest run after
     const bool split = G > 1 && !toy && BT >= 128;
@@ -1309,7 +1306,7 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
         }
         // each replica is its own set of workgroups here, so its list is rebuilt when it is
         // period steps old (or flagged), independently of the other replicas
-        if (cutoff_on && (need || any_hit || s - lastb >= period)) {
+        if (need || (cutoff_on && (any_hit || s - lastb >= period))) {
             lastb = s;
             block_spheres(S, xs, sph, tid, BT);
             __syncthreads();
@@ -1317,7 +1314,7 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
                 if (L0 + (tid & ~63) >= a1 * P) continue;          // whole wave past the group's atoms
                 const int L = L0 + tid, i = L / P, q = L % P;
                 const bool valid = L < a1 * P;
-                const int ngw = build_wave<4>(S, r, i, q, valid, (const GPR_LDS gv_f4 *)xs,
+                const int ngw = build_wave<4, true>(S, r, i, q, valid, (const GPR_LDS gv_f4 *)xs,
                                               (const GPR_LDS gv_f4 *)sph, (GPR_LDS int *)wscr + (tid >> 6) * WBLK,
                                               false);
                 if (valid && q == 0) {
