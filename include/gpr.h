@@ -38,7 +38,8 @@ typedef int32_t gpr_status;
 #define GPR_ENOMEM    (-2)  /* device or host allocation failed */
 #define GPR_EDEVICE   (-3)  /* HIP runtime error, missing device, or an in-kernel capacity limit */
 #define GPR_EPHASE    (-4)  /* call out of sequence (e.g. gpr_parallel_step before a converged gpr_dephase) */
-#define GPR_EUNSTABLE (-5)  /* a non-finite or overflowing position, velocity or force appeared */
+#define GPR_EUNSTABLE (-5)  /* a non-finite position or velocity, or a force component beyond
+                                 2.5e5 kJ/mol/nm, appeared */
 
 /* ---------------------------------------------------------------- system kinds */
 #define GPR_KIND_TOY2D      1  /* one particle in U(x,y) = (x^2-1)^2 + 2 y^2; z and v_z held at 0 */
