@@ -88,7 +88,7 @@ __device__ __forceinline__ BondedPlan bonded_plan(const Dev &S, int a0, int a1, 
 
 // Adds, for every term of the plan, the fixed-point forces on the atoms of [a0, a1) to
 // fa[3][len] (LDS, index a - a0); the energy of a term is counted by the range holding its
-// smallest atom.  Each thread takes up to four slots at a time and issues all their topology
+// smallest atom.  Each thread takes up to U slots at a time and issues all their topology
 // loads before computing any of them.  nthr must be a multiple of 64.
 template <class Pos, int U = 4>
 __device__ void bonded_range(const Dev &S, const BondedPlan &bp, const Pos &pos, int a0, int a1, long long *fa,
@@ -1208,6 +1208,7 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
     const int XT = BT >= 512 ? 128 : 64;                    // exchange threads (whole waves)
     long long *eacc = red + MAX_OBS * 8;
     bool alive = true;
+    bool pend = false;                                      // the previous step's closing B is due
 
     for (int step = 0; step < nsteps && alive; ++step) {
         const long long s = s0 + step;
@@ -1222,6 +1223,14 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
             float3 x = make_float3(xs[a].x, xs[a].y, xs[a].z);
             float3 v = make_float3(vs[l], vs[lmax + l], vs[2 * lmax + l]);
             const float3 F = make_float3(unfix_f(fa[l]), unfix_f(fa[lmax + l]), unfix_f(fa[2 * lmax + l]));
+            if (pend) {
+                // the previous step's closing B, deferred to here (same forces, same order)
+                const float im = iml[l];
+                v.x = kick(v.x, F.x, ik.h, im);
+                v.y = kick(v.y, F.y, ik.h, im);
+                v.z = kick(v.z, F.z, ik.h, im);
+                bad |= bad_force(F.x) || bad_force(F.y) || bad_force(F.z);
+            }
             integrate_baoa_k(ik, a, r, s, x, v, F, iml[l], sdl[l]);
             xs[a].x = x.x; xs[a].y = x.y; xs[a].z = x.z;
             vs[l] = v.x; vs[lmax + l] = v.y; vs[2 * lmax + l] = v.z;
@@ -1374,14 +1383,19 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
             }
         }
         __syncthreads();
-        for (int a = a0 + tid; a < a1; a += BT) {
-            const int l = a - a0;
-            const float im = iml[l], h = ik.h;
-            const float Fx = unfix_f(fa[l]), Fy = unfix_f(fa[lmax + l]), Fz = unfix_f(fa[2 * lmax + l]);
-            vs[l] = kick(vs[l], Fx, h, im);
-            vs[lmax + l] = kick(vs[lmax + l], Fy, h, im);
-            vs[2 * lmax + l] = kick(vs[2 * lmax + l], Fz, h, im);
-            if (bad_force(Fx) || bad_force(Fy) || bad_force(Fz)) atomicOr(&errp[ERR_UNSTABLE], 1);
+        // the closing B: here when the step's velocities are read (a sample, the end of the
+        // launch), else by the next step's integrator
+        pend = !(samp || step + 1 == nsteps);
+        if (!pend) {
+            for (int a = a0 + tid; a < a1; a += BT) {
+                const int l = a - a0;
+                const float im = iml[l], h = ik.h;
+                const float Fx = unfix_f(fa[l]), Fy = unfix_f(fa[lmax + l]), Fz = unfix_f(fa[2 * lmax + l]);
+                vs[l] = kick(vs[l], Fx, h, im);
+                vs[lmax + l] = kick(vs[lmax + l], Fy, h, im);
+                vs[2 * lmax + l] = kick(vs[2 * lmax + l], Fz, h, im);
+                if (bad_force(Fx) || bad_force(Fy) || bad_force(Fz)) atomicOr(&errp[ERR_UNSTABLE], 1);
+            }
         }
         if (samp) {
             __syncthreads();
