@@ -62,7 +62,9 @@ def kernel_source_hash():
     import hashlib
     import glob
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1807_02431_amd", "csrc", "*"))):
+    files = glob.glob(os.path.join(ROOT, "paper_1807_02431_amd", "csrc", "*"))
+    files.append(os.path.join(ROOT, "paper_1807_02431_amd", "build.py"))   # the compiler flags
+    for f in sorted(files):
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
             h.update(fh.read())
@@ -71,8 +73,8 @@ def kernel_source_hash():
 
 def measured_traffic(steps_per_launch):
     """HBM bytes per launch of the persistent kernel from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary, or None when the kernel sources or the launch length differ from the
-    ones the counters were taken on."""
+    WRITE_SIZE summary, or None when the kernel sources (or the compiler flags) or the launch
+    length differ from the ones the counters were taken on."""
     path = os.path.join(ROOT, "profiles", "k_persist_rl2432x64_hbm_traffic.md")
     if not os.path.exists(path):
         return None
