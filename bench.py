@@ -11,6 +11,8 @@ that the work per step is fixed).
 
 The product path (persistent kernel) is timed, then the plain one-launch-per-kernel-per-step
 path on the same system and seeds, launched from the host and replayed from a HIP graph.  Prints one JSON line.
+`value` comes from the first timed run of --steps steps; both paths are then timed --repeats - 1
+more times (each run continuing the trajectory), and the median over all runs is reported beside it.
 """
 from __future__ import annotations
 
@@ -191,6 +193,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed runs of --steps steps per path (value: the first; the median is reported too)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation measurement")
@@ -229,6 +233,7 @@ def main():
     t_p = timed_advance(ps, args.steps)
     kms, klaunch = ps.profile_read()
     ps.profile(False)
+    reps_p = [t_p] + [timed_advance(ps, args.steps) for _ in range(args.repeats - 1)]
     q_samples = [ps.get_state(r)[0] for r in (0, R // 2, R - 1)]
     pairs = float(np.mean([in_cutoff_pairs(spec, q) for q in q_samples]))
     frs = flops_per_replica_step(spec, pairs)
@@ -240,12 +245,14 @@ def main():
         pl = gpr.System(spec, path=gpr.PATH_PLAIN, stream=stream)
         pl.advance(args.warmup)
         t_pl = timed_advance(pl, args.steps)
+        reps_pl = [t_pl] + [timed_advance(pl, args.steps) for _ in range(args.repeats - 1)]
         pl.profile(True)
         pl.advance(min(args.steps, 1000))
         nb_ms, nb_n = pl.profile_read()
         pl.profile(False)
         plain = dict(replica_steps_per_s=R * args.steps / t_pl, atom_steps_per_s=R * n * args.steps / t_pl,
                      ms_per_step=1e3 * t_pl / args.steps, launches_per_step=3,
+                     median_ms_per_step=1e3 * float(np.median(reps_pl)) / args.steps,
                      pair_kernel_us=1e3 * nb_ms / max(nb_n, 1))
         print("# plain path replayed from a HIP graph: warmup %d, timing %d steps" % (args.warmup, args.steps),
               file=sys.stderr, flush=True)
@@ -285,6 +292,10 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "speedup_vs_plain": (value / plain["replica_steps_per_s"]) if plain else None,
+        "repeats": {"runs": len(reps_p), "ms_per_step": [1e3 * t / args.steps for t in reps_p],
+                    "median_ms_per_step": 1e3 * float(np.median(reps_p)) / args.steps,
+                    "median_replica_steps_per_s": R * args.steps / float(np.median(reps_p)),
+                    "median_speedup_vs_plain": (float(np.median(reps_pl)) / float(np.median(reps_p))) if plain else None},
         "plain_path": plain,
         "plain_path_graph": plain_graph,
         "dtype": "f32",
