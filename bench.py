@@ -204,7 +204,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the replicas of one system share one device "
-              "(multi-GPU replica sharding is not part of this build); run with --gpus 1",
+              "(sharding replicas over several GPUs is not implemented); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 
