@@ -279,6 +279,7 @@ def main():
     avg_launch_s = kms / 1e3 / max(klaunch, 1)
     achieved = frs * R * steps_per_launch / avg_launch_s / 1e12
     value = R * args.steps / t_p
+    traffic = measured_traffic(steps_per_launch)
     out = {
         "metric": "replica-steps/s & atom-steps/s, 2,432 atoms x 64 replicas, vs plain GPU path",
         "value": value,
@@ -304,7 +305,8 @@ def main():
                                "cutoff 1.0 nm reaction field, BAOAB dt 1 fs, t_GR 50, t_check 1000",
                    "n_atoms": n, "n_replicas": R, "path": "persistent"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(steps_per_launch),
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+                     "hbm_gbs": (traffic / avg_launch_s / 1e9) if traffic else None, "hbm_peak_gbs": PEAK_HBM_GBS,
                      "kernel": "k_persist", "avg_launch_us": avg_launch_s * 1e6,
                      "steps_per_launch": steps_per_launch, "flop_per_replica_step": frs,
                      "in_cutoff_pairs_per_replica": pairs},
