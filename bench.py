@@ -126,6 +126,52 @@ def cpu_baseline(spec, seconds=15.0):
                 atom_steps_per_s=R * steps * spec["n_atoms"] / dt)
 
 
+_ORACLE_WORKER = r"""
+import json, sys, time
+sys.path.insert(0, sys.argv[1])
+import gpr_synth as G
+import oracle
+o = oracle.System(G.config("rl2432", n_replicas=2))
+o.advance(1)
+start, seconds = float(sys.argv[2]), float(sys.argv[3])
+while time.time() < start:
+    time.sleep(0.01)
+n, t0 = 0, time.perf_counter()
+while time.perf_counter() - t0 < seconds:
+    o.advance(1)
+    n += 1
+print(json.dumps({"replica_steps": 2 * n, "seconds": time.perf_counter() - t0}))
+"""
+
+
+def cpu_baseline_all_cores(seconds=10.0, max_workers=16):
+    """The same FP64 oracle in one process per host core (at most 16), each stepping two
+    replicas of the workload from a common start time for about ``seconds``; the aggregate is
+    the replica-steps of all processes over the longest process's stepping time.  Run before
+    the process touches the GPU: the workers are started as child processes."""
+    import subprocess
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    workers = max(1, min(max_workers, ncpu))
+    start = time.time() + 3.0 + 0.05 * workers
+    procs = [subprocess.Popen([sys.executable, "-c", _ORACLE_WORKER, ROOT, repr(start), repr(seconds)],
+                              stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True)
+             for _ in range(workers)]
+    res = []
+    for p in procs:
+        out, _ = p.communicate(timeout=120 + seconds)
+        if p.returncode != 0:
+            return None
+        res.append(json.loads(out.strip().splitlines()[-1]))
+    rs = sum(r["replica_steps"] for r in res)
+    wall = max(r["seconds"] for r in res)
+    return dict(value=rs / wall, unit="replica-steps/s", cores=workers, kind="oracle",
+                sample="%d processes x 2 replicas of the 2,432-atom system, %d replica-steps in %.1f s (FP64, "
+                       "brute-force pairs)" % (workers, rs, wall))
+
+
 def differentiation_bench(spec, iters):
     """Forward (energy and forces) + backward (position and force-field parameter gradients) of
     all replicas through the device-pointer entry points, one batch per evaluation."""
@@ -208,6 +254,12 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    # the oracle on all host cores first, while this process has not touched the GPU
+    cpu_all = None
+    if not args.no_cpu and not args.copy_probe:
+        print("# oracle on all host cores", file=sys.stderr, flush=True)
+        cpu_all = cpu_baseline_all_cores()
+
     import torch
     if args.copy_probe:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
@@ -274,6 +326,8 @@ def main():
         batching = batching_bench(1000)
 
     cpu = None if args.no_cpu else cpu_baseline(spec)
+    if cpu is not None:
+        cpu["all_cores"] = cpu_all
 
     steps_per_launch = args.steps / max(klaunch, 1)
     avg_launch_s = kms / 1e3 / max(klaunch, 1)

@@ -78,3 +78,9 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert p.returncode == 2
     assert "one GPU" in p.stderr
+
+
+def test_oracle_on_all_cores_reports_an_aggregate():
+    r = bench.cpu_baseline_all_cores(seconds=1.0, max_workers=2)
+    assert r is not None and r["kind"] == "oracle" and r["unit"] == "replica-steps/s"
+    assert 1 <= r["cores"] <= 2 and r["value"] > 0
