@@ -73,11 +73,11 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(steps_per_launch):
-    """HBM bytes per launch of the persistent kernel from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary, or None when the kernel sources (or the compiler flags) or the launch
-    length differ from the ones the counters were taken on."""
-    path = os.path.join(ROOT, "profiles", "k_persist_rl2432x64_hbm_traffic.md")
+def _profile_figure(fname, key, steps_per_launch):
+    """A per-launch figure of the persistent kernel from a committed rocprofv3 summary, or None
+    when the kernel sources (or the compiler flags) or the launch length differ from the ones
+    the counters were taken on."""
+    path = os.path.join(ROOT, "profiles", fname)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -88,9 +88,19 @@ def measured_traffic(steps_per_launch):
                 kv[parts[0]] = parts[1]
     try:
         ok = kv["source_sha256"] == kernel_source_hash() and int(kv["steps_per_launch"]) == int(round(steps_per_launch))
-        return int(kv["hbm_bytes_per_launch"]) if ok else None
+        return int(kv[key]) if ok else None
     except (KeyError, ValueError):
         return None
+
+
+def measured_traffic(steps_per_launch):
+    """HBM bytes per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, copy-calibrated)."""
+    return _profile_figure("k_persist_rl2432x64_hbm_traffic.md", "hbm_bytes_per_launch", steps_per_launch)
+
+
+def measured_fp32_flop(steps_per_launch):
+    """FP32 FLOP executed per launch (rocprofv3 SQ_INSTS_VALU_{ADD,MUL,TRANS,FMA}_F32)."""
+    return _profile_figure("k_persist_rl2432x64_valu_counters.md", "fp32_flop_per_launch", steps_per_launch)
 
 
 def flops_per_replica_step(spec, pairs):
@@ -334,6 +344,7 @@ def main():
     achieved = frs * R * steps_per_launch / avg_launch_s / 1e12
     value = R * args.steps / t_p
     traffic = measured_traffic(steps_per_launch)
+    exec_flop = measured_fp32_flop(steps_per_launch)
     out = {
         "metric": "replica-steps/s & atom-steps/s, 2,432 atoms x 64 replicas, vs plain GPU path",
         "value": value,
@@ -361,6 +372,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "hbm_gbs": (traffic / avg_launch_s / 1e9) if traffic else None, "hbm_peak_gbs": PEAK_HBM_GBS,
+                     "executed_fp32_tflops": (exec_flop / avg_launch_s / 1e12) if exec_flop else None,
                      "kernel": "k_persist", "avg_launch_us": avg_launch_s * 1e6,
                      "steps_per_launch": steps_per_launch, "flop_per_replica_step": frs,
                      "in_cutoff_pairs_per_replica": pairs},
