@@ -117,9 +117,9 @@ typedef struct gpr_system_desc {
     int32_t n_atoms;             /* >= 1; the pair kernels hold a replica's positions and LJ
                                     parameters in LDS (24 bytes per atom), so creation fails with
                                     EINVAL past about 6,500 atoms on a 160 KiB-LDS device; the
-                                    persistent path, which also keeps its own atoms' velocities,
-                                    forces and lists in LDS, takes up to a few thousand atoms per
-                                    replica (gpr_set_path reports EINVAL beyond) */
+                                    persistent path, which also keeps its own atoms' velocities
+                                    and forces in LDS, takes up to about 4,600 atoms (8 workgroups
+                                    per replica; gpr_set_path reports EINVAL beyond) */
     int32_t n_replicas;          /* R >= 2 (replica 0 is the reference walker) */
 
     const double *mass;          /* [n_atoms], amu (> 0) */
