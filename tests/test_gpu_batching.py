@@ -78,7 +78,20 @@ def test_uneven_batch_of_768_replicas():
 
 
 def test_batch_advance_refuses_bad_input():
+    """A system twice, more than eight systems, a negative step count: EINVAL, nothing run."""
     gpr = _gpr()
     a = gpr.System(G.config("rl300", n_replicas=4), path=gpr.PATH_PERSISTENT)
-    with pytest.raises(gpr.GprError):
+    with pytest.raises(gpr.GprError) as e:
         gpr.batch_advance([a, a], 10)
+    assert e.value.code == -1
+    many = [gpr.System(G.config("chain22", n_replicas=2), path=gpr.PATH_PERSISTENT) for _ in range(9)]
+    with pytest.raises(gpr.GprError) as e:
+        gpr.batch_advance(many, 10)
+    assert e.value.code == -1
+    with pytest.raises(gpr.GprError) as e:
+        gpr.batch_advance([a], -1)
+    assert e.value.code == -1
+    assert a.global_step() == 0 and all(x.global_step() == 0 for x in many)
+    # eight is the most a shared launch takes
+    f = gpr.batch_advance(many[:8], 20)
+    assert len(f) == 8 and all(x.global_step() == 20 for x in many[:8])
