@@ -46,3 +46,22 @@ def test_create_without_device_fails_cleanly():
     import paper_1807_02431_amd as gpr
     with pytest.raises(gpr.GprError):
         gpr.System(G.toy2d())
+
+
+def test_missing_library_fails_loudly():
+    """Without the built library the binding raises instead of falling back to anything."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import paper_1807_02431_amd.gpr as g\n"
+            "g.LIB_PATH = '/nonexistent/libgpr_hip.so'\n"
+            "import gpr_synth as G\n"
+            "try:\n"
+            "    g.System(G.config('chain22', n_replicas=2))\n"
+            "except ImportError as e:\n"
+            "    print('raised', e)\n"
+            "    sys.exit(0)\n"
+            "sys.exit(1)\n") % ROOT
+    p = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert p.returncode == 0, p.stdout + p.stderr
+    assert "no fallback" in p.stdout
