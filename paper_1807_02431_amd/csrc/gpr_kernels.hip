@@ -346,12 +346,17 @@ __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool v
         __builtin_amdgcn_wave_barrier();
         int base = 0;
         for (int k0 = 0; k0 < cntm; k0 += UNR) {
-            int bbs[UNR];
+            // the next UNR blocks; past the last one (cntm) the last block again, whose test bits
+            // the mask `live` drops.  Every lane reads the same entries, so the block indices and
+            // what follows from them (candidate bases, the exclusion test below) stay scalar; all
+            // reads are in flight before the first use.
+            int raw[UNR], bb[UNR];
 #pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-                const int v = wblk[min(k0 + u, cntm - 1)];          // read unconditionally: no branch
-                bbs[u] = k0 + u < cntm ? v : -1;
-            }
+            for (int u = 0; u < UNR; ++u) raw[u] = wblk[min(k0 + u, cntm - 1)];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) bb[u] = __builtin_amdgcn_readfirstlane(raw[u]);
+            const int nlive = min(UNR, cntm - k0);
+            const unsigned live = nlive == UNR ? ~0u : (1u << (nlive * CPB)) - 1u;
             // (x, y, z) only: a 12-byte read leaves no unused destination register that the
             // compiler could reuse, and so wait for, before the read completes
             gv_f3 pj[UNR][CPB];
@@ -360,10 +365,10 @@ __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool v
             for (int u = 0; u < UNR; ++u)
 #pragma unroll
                 for (int t = 0; t < CPB; ++t)
-                    pj[u][t] = x3[bbs[u] >= 0 ? bbs[u] * BLK + q + t * P : n];
+                    pj[u][t] = x3[bb[u] * BLK + q + t * P];
             __builtin_amdgcn_sched_barrier(0);                  // keep the reads ahead of the tests
-            // a missing block reads the far-away atom n, which fails the distance test; a lane
-            // without an atom (its position also the far-away one) keeps no bit
+            // a slot past n in the last block holds a far-away position and fails the test; a
+            // lane without an atom (its position also the far-away one) keeps no bit
             unsigned tb = 0u;
 #pragma unroll
             for (int u = 0; u < UNR; ++u)
@@ -372,18 +377,18 @@ __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool v
                     const float dx = pi.x - pj[u][t].x, dy = pi.y - pj[u][t].y, dz = pi.z - pj[u][t].z;
                     tb |= (unsigned)(fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < rl2) << (u * CPB + t);
                 }
-            tb = valid ? tb : 0u;
+            tb = valid ? tb & live : 0u;
             // blocks that may hold the wave's atoms or their excluded partners (wave-uniform)
             bool self = false;
 #pragma unroll
             for (int u = 0; u < UNR; ++u)
-                self |= bbs[u] >= 0 && bbs[u] * BLK + BLK > iw - 32 && bbs[u] * BLK < iw + 16 + 32;
+                self |= u < nlive && bb[u] * BLK + BLK > iw - 32 && bb[u] * BLK < iw + 16 + 32;
             if (self) {
 #pragma unroll
                 for (int u = 0; u < UNR; ++u)
 #pragma unroll
                     for (int t = 0; t < CPB; ++t) {
-                        const int off = bbs[u] * BLK + q + t * P - i + 32;
+                        const int off = bb[u] * BLK + q + t * P - i + 32;
                         const unsigned drop = (unsigned)((unsigned)off < 64u) & (unsigned)((ex >> (off & 63)) & 1ull);
                         tb &= ~(drop << (u * CPB + t));
                     }
