@@ -291,8 +291,10 @@ __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool v
     static_assert(BATCH % UNR == 0, "a batch holds whole groups of UNR blocks");
     unsigned long long word = 0ull, bits = 0ull;
     int cnt = 0;
+    GPR_GLOBAL unsigned long long *Lw = L;                      // where the next full group goes
     // entries kept in bits, whose blocks are wblk[base ...]; entry cnt is 16-bit word cnt % 4 of
-    // group cnt / 4, and a group is stored once complete
+    // group cnt / 4: each entry is shifted in at the top of the group word, so that after four
+    // they sit in order from its low end, and the group is stored once complete
     auto emit = [&](int base) {
         __builtin_amdgcn_wave_barrier();
         // two halves of 16 blocks (32 bits) each, entries in ascending order
@@ -314,12 +316,12 @@ __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool v
 #pragma unroll
                 for (int e = 0; e < UNR; ++e) {
                     if (!has[e]) continue;
-                    const int j = bk[e] * BLK + q + (k[e] % CPB) * P;
+                    const unsigned j = (unsigned)(bk[e] * BLK + q + (k[e] % CPB) * P);
                     if (cnt < cap) {
-                        word |= (unsigned long long)j << (16 * (cnt & 3));
+                        word = (word >> 16) | ((unsigned long long)j << 48);
                         if ((cnt & 3) == 3) {
-                            gst(L + (size_t)(cnt >> 2) * stride, word);
-                            word = 0ull;
+                            gst(Lw, word);
+                            Lw += stride;
                         }
                     }
                     ++cnt;
@@ -404,8 +406,8 @@ __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool v
     if (!valid) return 0;
     const int ng = min((cnt + 3) >> 2, S.Kg);
     if ((cnt & 3) != 0 && cnt < cap) {
-        for (int k = cnt & 3; k < 4; ++k) word |= (unsigned long long)n << (16 * k);
-        gst(L + (size_t)(cnt >> 2) * stride, word);
+        for (int k = cnt & 3; k < 4; ++k) word = (word >> 16) | ((unsigned long long)(unsigned)n << 48);
+        gst(Lw, word);
     }
     // PAD: the four sub-lists of an atom padded to the same number of groups with the
     // far-away atom n (exact zeros), so that one count (the largest, returned) serves the
