@@ -65,6 +65,8 @@ struct gro_sys {
     double shift[GRO_NMAXOBS];
     /* parallel step, resumable */
     int64_t par_M;
+    /* steps taken by gro_advance since creation: its sampling and check schedule */
+    int64_t adv_t;
 };
 
 static char g_err[512];
@@ -787,14 +789,23 @@ int gro_observe(const gro_sys *S, double *obs, int32_t *state)
  * With samples taken at the right end of each t_GR interval, t^-1 int_0^t O ds is the
  * sample mean and the time integrals of Eq. 3 are sample means.  Writing Ob_k = S1_k/n
  * (shifted by the common c), the numerator of Eq. 3 is mean_k(S2_k/n) - (mean_k Ob_k)^2
- * and the denominator mean_k(S2_k/n - Ob_k^2).  Means over workers use a pairwise sum
- * (halving, lower half first) so that the result is reproducible bit for bit. */
+ * and the denominator mean_k(S2_k/n - Ob_k^2).  The paper fixes no summation order; sums
+ * over workers use one canonical pairwise tree, so that the result is reproducible bit for
+ * bit: the m terms are padded with zeros to the next power of two p and each node of the
+ * tree adds its lower half to its upper half, (x[lo .. lo+p/2) sum) + (x[lo+p/2 .. lo+p) sum). */
+static double pairwise_pow2(const double *x, int m, int lo, int p)
+{
+    if (p == 1) return lo < m ? x[lo] : 0.0;
+    int h = p / 2;
+    return pairwise_pow2(x, m, lo, h) + pairwise_pow2(x, m, lo + h, h);
+}
+
 static double pairwise(const double *x, int m)
 {
     if (m <= 0) return 0.0;
-    if (m == 1) return x[0];
-    int h = m / 2;
-    return pairwise(x, h) + pairwise(x + h, m - h);
+    int p = 1;
+    while (p < m) p *= 2;
+    return pairwise_pow2(x, m, 0, p);
 }
 
 int gro_rhat(int32_t nw, int32_t n_obs, int64_t n, const double *S1, const double *S2, double *rhat)
@@ -1116,40 +1127,49 @@ int gro_parallel_step(gro_sys *S, int64_t max_checks, gro_exit_result *o)
 {
     if (S->phase == PH_CONVERGED) { S->phase = PH_PARALLEL; S->par_M = 0; }
     else if (S->phase != PH_PARALLEL) { set_err("parallel step needs a converged dephasing"); return GRO_EPHASE; }
+    int64_t *fec = (int64_t *)malloc(sizeof(int64_t) * S->R);
+    if (!fec) return GRO_ENOMEM;
     int64_t checks = 0;
+    int rc = GRO_BUDGET;
     while (checks < max_checks) {
-        for (int k = 0; k < S->tcp; k++) {
-            int e = step_all(S, S->R);
-            if (e) return e;
-        }
+        int e = GRO_OK;
+        for (int k = 0; k < S->tcp && e == GRO_OK; k++) e = step_all(S, S->R);
+        if (e) { rc = e; break; }
         S->par_M += 1;
         checks += 1;
-        int k = 0;
-        for (int r = 0; r < S->R; r++)
-            if (gro_state_of(S, Q(S, r)) != S->omega) { k = r + 1; break; }
-        if (k == 0) continue;
-        int64_t tau = ((int64_t)S->R * (S->par_M - 1) + k) * S->tcp;
+        /* first exit check of each replica: earlier checks found none, so every replica
+         * outside Omega now first left it at check M; Eq. 5 then picks (M, k, tau) */
+        for (int r = 0; r < S->R; r++) fec[r] = gro_state_of(S, Q(S, r)) != S->omega ? S->par_M : 0;
+        int64_t M, tau;
+        int32_t k;
+        if (gro_exit_vote(S->R, fec, S->tcp, &M, &k, &tau) != GRO_OK) continue;
         S->tsim += tau;
         if (k != 1) copy_replica(S, 0, k - 1);
         int st = gro_state_of(S, Q(S, 0));
-        o->M = S->par_M; o->k = k; o->to_state = st; o->tau_steps = tau; o->tau = (double)tau * S->dt;
+        o->M = M; o->k = k; o->to_state = st; o->tau_steps = tau; o->tau = (double)tau * S->dt;
         S->omega = st;
         S->phase = PH_IDLE;
-        return GRO_OK;
+        rc = GRO_OK;
+        break;
     }
-    return GRO_BUDGET;
+    free(fec);
+    return rc;
 }
 
 /* ------------------------------------------------------------------ fixed-work stepping
  * All replicas step nsteps; observables of the workers are accumulated every t_GR and
- * every replica is tested every t_check_dephase; nothing is acted on. */
+ * every replica is tested every t_check_dephase; nothing is acted on.  The schedule runs on
+ * the steps taken by every call since creation (adv_t), so that several short calls sample
+ * and test as one long call would; fec[r] receives the index (counted over all calls) of
+ * the first check of this call that found replica r outside Omega, 0 if none. */
 int gro_advance(gro_sys *S, int64_t nsteps, int64_t *fec)
 {
     int64_t *first = (int64_t *)calloc(S->R, sizeof(int64_t));
     if (!first) return GRO_ENOMEM;
-    for (int64_t t = 1; t <= nsteps; t++) {
+    for (int64_t k = 0; k < nsteps; k++) {
         int e = step_all(S, S->R);
         if (e) { free(first); return e; }
+        const int64_t t = ++S->adv_t;
         if (t % S->t_gr == 0) accumulate_workers(S);
         if (t % S->tcd == 0) {
             for (int r = 0; r < S->R; r++)

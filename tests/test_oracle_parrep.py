@@ -211,3 +211,51 @@ def test_toy_gen_parrep_matches_direct_simulation():
         return (2 * m * x.mean() / stats.chi2.ppf(0.975, 2 * m), 2 * m * x.mean() / stats.chi2.ppf(0.025, 2 * m))
     a, b = ci(dd), ci(gg)
     assert a[0] < b[1] and b[0] < a[1]
+
+
+def _chain6(seed):
+    """The chain of the 22-atom workload cut to six atoms (phi = (1,2,3,4), psi = (2,3,4,5),
+    the same force field and state = (phi, psi) quadrant; chain seed 5) with the n = 2 terms
+    raised to k2 = 10 kJ/mol, so that each quadrant is metastable with exits every ~6,000
+    steps into both neighbouring quadrants (the 22-atom chain exits every ~4e5 steps, out of
+    reach of a CPU test, and almost only through psi).  ``seed`` is the noise seed."""
+    return dict(G.chain(seed=5, n_atoms=6, n_replicas=8, k2=10.0, t_gr=10, t_check=50, t_check_parallel=50),
+                seed=seed)
+
+
+@pytest.mark.slow
+def test_chain_exit_states_match_direct_simulation():
+    """Exit states (Sec. 2.2: the quadrant the walker leaves into) sampled by Gen.ParRep have
+    the law of those of direct simulation.  For each state left, a chi-square test of
+    homogeneity of the destination counts of the two runs (destinations seen fewer than ten
+    times in both runs together pooled); the statistics and degrees of freedom are summed over
+    the four states into one test.  Same exit-check period on both sides; the exit durations
+    agree by a two-sample KS test."""
+    from collections import Counter
+    n = 400
+    d = direct_exits(oracle.System(_chain6(105)), n)
+    g = gen_parrep_exits(oracle.System(_chain6(205)), n, t_corr=3000)
+    cd = Counter((x[1], x[2]) for x in d)
+    cg = Counter((x[1], x[2]) for x in g)
+    assert all(a != b for a, b in list(cd) + list(cg))
+    stat, dof, multi = 0.0, 0, 0
+    for f in range(4):
+        dests = sorted({b for a, b in list(cd) + list(cg) if a == f})
+        main = [b for b in dests if cd[(f, b)] + cg[(f, b)] >= 10]
+        rest = [b for b in dests if b not in main]
+        rows = [[c[(f, b)] for b in main] + ([sum(c[(f, b)] for b in rest)] if rest else []) for c in (cd, cg)]
+        table = np.array(rows)
+        table = table[:, table.sum(0) > 0]
+        if table.shape[1] < 2:
+            continue
+        multi += 1
+        c2, _, k, _ = stats.chi2_contingency(table, correction=False)
+        stat += c2
+        dof += k
+    assert multi == 4                                  # every state has two or more destinations
+    assert stats.chi2.sf(stat, dof) > 0.01, (stat, dof, cd, cg)
+    kinds = Counter(x[3] for x in g)
+    assert kinds["parallel"] > n // 10 and kinds["dephase"] > n // 10
+    dd = np.array([x[0] for x in d], float)
+    gg = np.array([x[0] for x in g], float)
+    assert stats.ks_2samp(dd, gg).pvalue > 0.01
