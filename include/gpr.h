@@ -120,7 +120,8 @@ typedef struct gpr_system_desc {
                                     persistent path, which also keeps its own atoms' velocities
                                     and forces in LDS, takes up to about 4,600 atoms (8 workgroups
                                     per replica; gpr_set_path reports EINVAL beyond) */
-    int32_t n_replicas;          /* R >= 2 (replica 0 is the reference walker) */
+    int32_t n_replicas;          /* 2 <= R <= 4096 (replica 0 is the reference walker); the check kernel
+                                    keeps one survivor index per replica in LDS */
 
     const double *mass;          /* [n_atoms], amu (> 0) */
     const double *pos;           /* [3][n_atoms] SoA, nm: x[0..n), y[0..n), z[0..n) */
@@ -338,10 +339,12 @@ gpr_status gpr_set_state(gpr_system *sys, int32_t r, const double *q, const doub
 
 /* Advances all replicas nsteps BAOAB steps, sampling the observables of replicas >= 1 every
  * t_gr steps and testing the state of every replica every t_check_dephase steps, with
- * nothing acted on: no branching, no phase change, clock unchanged.  first_exit_check
- * ([R] host int64, or NULL) receives, per replica, the 1-based index of the first check
- * within this call at which state != Omega (0 if none).  The fixed-work stepping loop of
- * the measurement harness. */
+ * nothing acted on: no branching, no phase change, clock unchanged.  The sampling and test
+ * schedule runs on the steps taken by all gpr_advance / gpr_batch_advance calls on the
+ * handle since creation, so that several short calls sample and test as one long call
+ * does.  first_exit_check ([R] host int64, or NULL) receives, per replica, the index
+ * (1-based, counted over all calls) of the first check within this call at which
+ * state != Omega (0 if none).  The fixed-work stepping loop of the measurement harness. */
 gpr_status gpr_advance(gpr_system *sys, int64_t nsteps, int64_t *first_exit_check);
 
 /* gpr_advance of several systems (1 to 8, each its own handle, all on one stream and able to
@@ -388,8 +391,10 @@ gpr_status gpr_fv_plan(uint64_t seed, int64_t step, int32_t R, const uint8_t *ex
 
 /* Gelman-Rubin statistic (Eq. 3) over nw workers from shifted sums: Ob_k = S1[k]/n,
  * num = mean_k(S2[k]/n) - (mean_k Ob_k)^2, den = mean_k(S2[k]/n - Ob_k^2), rhat = num/den
- * (+inf if den <= 0).  Means are pairwise sums over k (halving recursion, lower half first),
- * without FMA contraction.  S1, S2: [nw][n_obs]; rhat: [n_obs]. */
+ * (+inf if den <= 0).  Means are pairwise sums over k on one canonical tree: the nw terms
+ * padded with zeros to the next power of two, each node the sum of its lower and its upper
+ * half; no FMA contraction.  The routine is the one the dephasing check runs.  S1, S2:
+ * [nw][n_obs]; rhat: [n_obs]; 1 <= n_obs <= 64. */
 gpr_status gpr_rhat(int32_t nw, int32_t n_obs, int64_t n, const double *S1, const double *S2, double *rhat);
 
 /* Parallel-step vote (Eq. 5): first_exit_check[R] (0 = no exit yet, else 1-based check

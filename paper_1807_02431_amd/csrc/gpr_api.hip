@@ -54,6 +54,7 @@ struct gpr_system {
     int dc_from = -1, dc_omega = -1;
     long long dc_resid = 0, dc_steps = 0;
     long long dp_t = 0, nsamp = 0, n_branch = 0;
+    long long adv_t = 0;       // steps taken by gpr_advance / gpr_batch_advance: their sampling and check phase
     long long par_M = 0;
     // original ParRep dephasing: start configuration, samples, per-replica progress
     float *snap_x = nullptr, *snap_v = nullptr, *samp_x = nullptr, *samp_v = nullptr;
@@ -468,7 +469,7 @@ static gpr_status run_steps(gpr_system *S, int nrep, long long nsteps, long long
             PersistItem &it = pb.it[0];
             it.s0 = S->s + done;
             it.nsteps = chunk;
-            it.t0 = (int)(t0 + done);
+            it.t0 = (int)((t0 + done) % S->t_gr);        // the device uses it modulo t_GR only
             it.sample = sample ? 1 : 0;
             it.state_end = (state_end && last) ? 1 : 0;
             for (int k = 0; k < rounds; ++k) {
@@ -509,15 +510,14 @@ static gpr_status run_steps(gpr_system *S, int nrep, long long nsteps, long long
     return GPR_OK;
 }
 
-static gpr_status check(gpr_system *S, int mode, int nrep, int check_index)
+// one launch: bookkeeping by block (0, 0), and with CHK_DEPHASE the clone-on-kill copies by
+// the blocks of each killed worker's row
+static gpr_status check(gpr_system *S, int mode, int nrep, long long check_index)
 {
-    hipLaunchKernelGGL(k_check, dim3(1), dim3(64), 0, S->stream, S->d_dev, mode, S->s, S->omega, nrep, S->nsamp,
-                       check_index, S->st_dev, S->donor, S->surv, S->fec);
+    const dim3 grid = mode == CHK_DEPHASE ? dim3((3 * S->np + 255) / 256, nrep) : dim3(1, 1);
+    hipLaunchKernelGGL(k_check, grid, dim3(256), sizeof(int) * nrep, S->stream, S->d_dev, mode, S->s, S->omega, nrep,
+                       S->nsamp, check_index, (long long)S->tcp, S->st_dev, S->donor, S->surv, S->fec);
     LAUNCHCHK(S);
-    if (mode == CHK_DEPHASE) {
-        hipLaunchKernelGGL(k_clone, dim3((3 * S->np + 255) / 256, nrep), dim3(256), 0, S->stream, S->d_dev, S->donor, 1);
-        LAUNCHCHK(S);
-    }
     HIPCHK(S, hipMemcpyAsync(S->st_host, S->st_dev, sizeof(Status), hipMemcpyDeviceToHost, S->stream));
     HIPCHK(S, hipStreamSynchronize(S->stream));
     HIPCHK(S, prof_collect(S));
@@ -766,6 +766,7 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
     HIPCHK(S, dalloc(S, &d.nbc, (size_t)R * np * P));
     HIPCHK(S, dalloc(S, &d.guard, 2 * R));
     HIPCHK(S, dalloc(S, &d.need_build, R));
+    HIPCHK(S, dalloc(S, &d.list_pad, R));
     HIPCHK(S, dalloc(S, &d.last_build, 2 * R));
     HIPCHK(S, dalloc(S, &d.clock, 2));
     HIPCHK(S, dalloc(S, &d.err, 4));
@@ -946,7 +947,7 @@ extern "C" gpr_status gpr_system_create(const gpr_system_desc *D, gpr_system **o
     *out = nullptr;
     if (!D) return fail(nullptr, GPR_EINVAL, "descriptor is NULL");
     if (D->kind != GPR_KIND_TOY2D && D->kind != GPR_KIND_MOLECULAR) return fail(nullptr, GPR_EINVAL, "bad kind");
-    if (D->n_atoms < 1 || D->n_atoms > 65535 || D->n_replicas < 2 || !D->mass || !D->pos)
+    if (D->n_atoms < 1 || D->n_atoms > 65535 || D->n_replicas < 2 || D->n_replicas > 4096 || !D->mass || !D->pos)
         return fail(nullptr, GPR_EINVAL, "bad sizes or missing arrays");
     if (D->kind == GPR_KIND_TOY2D && D->n_atoms != 1) return fail(nullptr, GPR_EINVAL, "the toy system has one particle");
     if (!(D->dt > 0) || !(D->kT > 0) || !(D->gamma >= 0)) return fail(nullptr, GPR_EINVAL, "bad dynamics parameters");
@@ -1589,17 +1590,18 @@ extern "C" gpr_status gpr_parallel_step(gpr_system *S, int64_t max_checks, gpr_e
         if (rc) return rc;
         S->par_M += 1;
         checks += 1;
-        rc = check(S, CHK_PARALLEL, S->R, 0);
+        rc = check(S, CHK_PARALLEL, S->R, S->par_M);
         if (rc) return rc;
         const int k = S->st_host->k;
         if (k == 0) continue;
-        const long long tau = ((long long)S->R * (S->par_M - 1) + k) * S->tcp;
+        // M, k and tau of Eq. 5, voted on the device
+        const long long tau = S->st_host->tau;
         S->tsim += tau;
         if (k != 1) {
             rc = copy_replica(S, 0, k - 1);
             if (rc) return rc;
         }
-        o->M = S->par_M; o->k = k; o->to_state = S->st_host->to_state; o->tau_steps = tau; o->tau = (double)tau * S->dt;
+        o->M = S->st_host->M; o->k = k; o->to_state = S->st_host->to_state; o->tau_steps = tau; o->tau = (double)tau * S->dt;
         S->omega = S->st_host->to_state;
         S->phase = PH_IDLE;
         HIPCHK(S, hipStreamSynchronize(S->stream));
@@ -1613,16 +1615,20 @@ extern "C" gpr_status gpr_advance(gpr_system *S, int64_t nsteps, int64_t *first_
     if (!S) return fail(nullptr, GPR_EINVAL, "NULL system");
     if (nsteps < 0) return fail(S, GPR_EINVAL, "nsteps < 0");
     HIPCHK(S, hipMemsetAsync(S->fec, 0, sizeof(long long) * S->R, S->stream));
-    long long t = 0;
-    while (t < nsteps) {
-        const long long k = std::min<long long>(S->tcd - t % S->tcd, nsteps - t);
+    // the sampling (every t_GR) and check (every t_check_dephase) schedule runs on the steps
+    // counted over all calls, so that short calls sample and check as one long call would
+    long long t = S->adv_t;
+    const long long end = S->adv_t + nsteps;
+    while (t < end) {
+        const long long k = std::min<long long>(S->tcd - t % S->tcd, end - t);
         const bool at_check = (t + k) % S->tcd == 0;
         gpr_status rc = run_steps(S, S->R, k, t, true, at_check);
         if (rc) return rc;
         S->nsamp += count_samples(t, t + k, S->t_gr);
         t += k;
+        S->adv_t = t;
         if (at_check) {
-            rc = check(S, CHK_ADVANCE, S->R, (int)(t / S->tcd));
+            rc = check(S, CHK_ADVANCE, S->R, t / S->tcd);
             if (rc) return rc;
         }
     }
@@ -1718,6 +1724,7 @@ extern "C" gpr_status gpr_batch_advance(gpr_system *const *systems, int32_t nsys
     if (boff > capacity) return fail(S0, GPR_EINVAL, "the systems' workgroups do not fit on the device at once");
     const int nblocks = boff;
     std::vector<long long> t(nsys, 0);
+    for (int k = 0; k < nsys; ++k) t[k] = systems[k]->adv_t;
     for (int k = 0; k < nsys; ++k)
         HIPCHK(systems[k], hipMemsetAsync(systems[k]->fec, 0, sizeof(long long) * systems[k]->R, stream));
     long long done = 0;
@@ -1730,7 +1737,7 @@ extern "C" gpr_status gpr_batch_advance(gpr_system *const *systems, int32_t nsys
             PersistItem &it = pb.it[slot[k]];
             it.s0 = S->s;
             it.nsteps = (int)kstep;
-            it.t0 = (int)t[k];
+            it.t0 = (int)(t[k] % S->t_gr);
             it.sample = 1;
             it.state_end = (t[k] + kstep) % S->tcd == 0 ? 1 : 0;
             if (S->groups > 1) HIPCHK(S, hipMemsetAsync(S->d.sync, 0, sizeof(int) * 64 * S->R, stream));
@@ -1742,8 +1749,9 @@ extern "C" gpr_status gpr_batch_advance(gpr_system *const *systems, int32_t nsys
             S->s += kstep;
             S->nsamp += count_samples(t[k], t[k] + kstep, S->t_gr);
             t[k] += kstep;
+            S->adv_t = t[k];
             if (t[k] % S->tcd == 0) {
-                rc = check(S, CHK_ADVANCE, S->R, (int)(t[k] / S->tcd));
+                rc = check(S, CHK_ADVANCE, S->R, t[k] / S->tcd);
                 if (rc) return rc;
             }
         }
@@ -1815,7 +1823,7 @@ extern "C" gpr_status gpr_fv_plan(uint64_t seed, int64_t step, int32_t R, const 
     TMPCHK(tmp_alloc(t.v, &dn, R));
     TMPCHK(tmp_alloc(t.v, &sv, R));
     TMPCHK(hipMemcpy(ex, exited, R, hipMemcpyHostToDevice));
-    hipLaunchKernelGGL(k_fvplan_test, dim3(1), dim3(64), 0, 0, (uint32_t)seed, (uint32_t)(seed >> 32), (long long)step, R, ex, dn, sv);
+    hipLaunchKernelGGL(k_fvplan_test, dim3(1), dim3(256), 0, 0, (uint32_t)seed, (uint32_t)(seed >> 32), (long long)step, R, ex, dn, sv);
     TMPCHK(hipGetLastError());
     TMPCHK(hipMemcpy(donor, dn, sizeof(int) * R, hipMemcpyDeviceToHost));
     return GPR_OK;
@@ -1834,7 +1842,7 @@ extern "C" gpr_status gpr_rhat(int32_t nw, int32_t n_obs, int64_t n, const doubl
     TMPCHK(tmp_alloc(t.v, &o, n_obs));
     TMPCHK(hipMemcpy(a, S1, cnt * 8, hipMemcpyHostToDevice));
     TMPCHK(hipMemcpy(b, S2, cnt * 8, hipMemcpyHostToDevice));
-    hipLaunchKernelGGL(k_rhat_test, dim3(1), dim3(64), 0, 0, nw, n_obs, (long long)n, a, b, o);
+    hipLaunchKernelGGL(k_rhat_test, dim3(n_obs), dim3(64), 0, 0, nw, n_obs, (long long)n, a, b, o);
     TMPCHK(hipGetLastError());
     TMPCHK(hipMemcpy(rhat, o, 8 * (size_t)n_obs, hipMemcpyDeviceToHost));
     return GPR_OK;
@@ -1848,7 +1856,7 @@ extern "C" gpr_status gpr_exit_vote(int32_t R, const int64_t *fec, int64_t t_che
     TMPCHK(tmp_alloc(t.v, &f, R));
     TMPCHK(tmp_alloc(t.v, &o, 3));
     TMPCHK(hipMemcpy(f, fec, 8 * (size_t)R, hipMemcpyHostToDevice));
-    hipLaunchKernelGGL(k_vote_test, dim3(1), dim3(64), 0, 0, R, f, (long long)t_check, o);
+    hipLaunchKernelGGL(k_vote_test, dim3(1), dim3(256), 0, 0, R, f, (long long)t_check, o);
     TMPCHK(hipGetLastError());
     long long h[3];
     TMPCHK(hipMemcpy(h, o, sizeof h, hipMemcpyDeviceToHost));

@@ -89,6 +89,8 @@ struct Dev {
     int Kg;                                // capacity of one sub-list, in groups of four
     int *guard;                            // [2][R] displacement guard flags by step parity
     int *need_build;                       // [R]
+    int *list_pad;                         // [R] 1: the replica's lists are the persistent search's (sub-lists
+                                           // of an atom padded to one count), 0: the plain search's
     long long *last_build;                 // [2][R] step of the last pair-list build, by step parity
     long long *clock;                      // [2]: global step s and steps t of the current call (device-clocked plain steps)
     int *err;                              // [4] error flags

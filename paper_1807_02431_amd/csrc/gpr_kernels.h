@@ -15,6 +15,8 @@ struct Status {
     int k;              // parallel step: 1-based index of the first exiting replica, 0 if none
     int to_state;       // state of replica 0 (or of replica k-1 in the parallel step)
     int err[4];
+    long long M;        // parallel step: check index of the first exit (Eq. 5), 0 if none
+    long long tau;      // parallel step: (R (M - 1) + k) t_check steps (Eq. 5)
     double rhat[MAX_OBS];
 };
 
@@ -59,8 +61,8 @@ __global__ void k_grad_terms(const Dev *__restrict__ Sp, const double *w);
 __global__ void k_grad_finish(const Dev *__restrict__ Sp, double *d_eps, double *d_sigma, double *d_charge, double *d_tk);
 __global__ void k_unfix_out(const Dev *__restrict__ Sp, double *energy, float *forces);
 __global__ void k_weighted_dx(const Dev *__restrict__ Sp, const double *w, float *dx);
-__global__ void k_check(const Dev *__restrict__ Sp, int mode, long long s, int omega, int nrep, long long nsamp, int check_index,
-                        Status *st, int *donor, int *surv, long long *fec);
+__global__ void k_check(const Dev *__restrict__ Sp, int mode, long long s, int omega, int nrep, long long nsamp,
+                        long long check_index, long long t_check, Status *st, int *donor, int *surv, long long *fec);
 __global__ void k_clone(const Dev *__restrict__ Sp, const int *donor, int acc_mode);
 __global__ void k_init_vel(const Dev *__restrict__ Sp, float kT);
 __global__ void k_noise_test(uint32_t k0, uint32_t k1, int replica, long long step, int stream, int n,

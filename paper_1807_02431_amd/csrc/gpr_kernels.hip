@@ -835,10 +835,12 @@ __global__ void __launch_bounds__(1024) k_nonbonded(const Dev *__restrict__ Sp, 
         if (blockIdx.x == 0 && tid == 0) {
             S.guard[((s + 1) & 1) * S.R + r] = 0;
             S.last_build[((s + 1) & 1) * S.R + r] = rebuild ? s : lb;
+            if (rebuild) S.list_pad[r] = 0;
         }
     } else if (blockIdx.x == 0 && tid == 0) {
         S.last_build[r] = s;
         S.last_build[S.R + r] = s;
+        S.list_pad[r] = 0;
     }
     __syncthreads();
     const int i = blockIdx.x * (nthr / P) + tid / P;
@@ -1196,12 +1198,27 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
         sdl[l] = a < a1 ? sdv[a] : 0.f;
     }
     // the pair loop below runs each atom's four sub-lists to one count, which needs lists
-    // padded as this kernel's search writes them: the first step of every launch builds them
-    bool need = S.kind != KIND_TOY;
-    long long lastb = S.last_build[(s0 & 1) * S.R + r];     // step of the last pair-list build
-    __syncthreads();
+    // padded as this kernel's search writes them: lists from the plain path's search, or a
+    // replica marked for a rebuild (a new configuration), are rebuilt at the first step;
+    // padded lists from an earlier launch are kept, their counts and order recomputed
     const bool toy = S.kind == KIND_TOY;
+    bool need = !toy && (S.need_build[r] != 0 || S.list_pad[r] == 0);
+    long long lastb = S.last_build[(s0 & 1) * S.R + r];     // step of the last pair-list build
     const int nl = a1 - a0, nslot = 16 * ((nl + 15) >> 4);
+    if (!toy && !need) {
+        const size_t stride = (size_t)np * P;
+        const GPR_GLOBAL unsigned short *cnt = gconst(S.nbc) + (size_t)r * stride;
+        for (int l = tid; l < nl; l += BT) {
+            const int i = a0 + l;
+            int k = 0;
+#pragma unroll
+            for (int q = 0; q < P; ++q) k = max(k, (int)cnt[(size_t)i * P + q]);
+            keyl[l] = (unsigned short)k;
+        }
+        __syncthreads();
+        order_atoms(keyl, perm, hist, nl, tid, BT);
+    }
+    __syncthreads();
     // descriptor fields used every step, held in registers for the launch
     const IntConsts ik = int_consts(S);
     const int t_gr = S.t_gr, need_energy = S.need_energy, cutoff_on = S.cutoff_on, period = S.period;
@@ -1340,6 +1357,7 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
                 }
             }
             order_atoms(keyl, perm, hist, nl, tid, BT);
+            if (need && g == 0 && tid == 0) S.list_pad[r] = 1;
             need = false;
         }
         if (!split) {
@@ -1521,160 +1539,255 @@ __global__ void __launch_bounds__(1024) k_persist_batch(PersistBatch pb)
 
 
 // ================================================================== Gen.ParRep bookkeeping
-// Pairwise sum over k = 0..m-1 of f(k): the halving recursion (lower half first) unrolled
-// with an explicit stack, so that the rounding matches a recursive evaluation exactly.
+// Sums over workers follow one canonical pairwise tree: the m terms padded with zeros to the
+// next power of two p, each node the sum of its lower half and its upper half.  A wave
+// evaluates it with lane l holding the c = max(1, p / 64) consecutive terms [l c, l c + c):
+// their subtree inside the lane, then xor shuffles at partner distances 1, 2, 4, ... over the
+// lanes that hold terms, which form exactly the upper levels of the tree (the two lanes of a
+// pair add the same two values in either order, with identical bits).
+constexpr int TREE_C = 16;                 // terms per lane summed in registers
+
+// subtree of the c (a power of two) terms f(base .. base + c), those >= m being zero
 template <class Fn>
-__device__ double pairwise_sum(int m, Fn f)
+__device__ __forceinline__ double lane_tree16(Fn f, int m, int base, int c)
 {
-    if (m <= 0) return 0.0;
-    int lo_s[40], m_s[40], st_s[40];
-    double left_s[40];
-    int sp = 1;
-    lo_s[0] = 0; m_s[0] = m; st_s[0] = 0;
-    double val = 0.0;
-    bool ret = false;
-    for (;;) {
-        const int t = sp - 1;
-        if (!ret) {
-            if (m_s[t] == 1) {
-                val = f(lo_s[t]);
-                ret = true;
-                if (--sp == 0) return val;
-                continue;
-            }
-            st_s[t] = 0;
-            lo_s[sp] = lo_s[t]; m_s[sp] = m_s[t] / 2; st_s[sp] = 0; ++sp;
-        } else if (st_s[t] == 0) {
-            left_s[t] = val;
-            st_s[t] = 1;
-            const int h = m_s[t] / 2;
-            lo_s[sp] = lo_s[t] + h; m_s[sp] = m_s[t] - h; st_s[sp] = 0; ++sp;
-            ret = false;
-        } else {
-            val = left_s[t] + val;
-            if (--sp == 0) return val;
-        }
-    }
+    double e[TREE_C];
+#pragma unroll
+    for (int i = 0; i < TREE_C; ++i) e[i] = (i < c && base + i < m) ? f(base + i) : 0.0;
+#pragma unroll
+    for (int w = 1; w < TREE_C; w <<= 1)
+#pragma unroll
+        for (int i = 0; i + w < TREE_C; i += 2 * w)
+            if (w < c) e[i] += e[i + w];
+    return e[0];
 }
 
-// Gelman-Rubin R-hat (Eq. 3) of one observable over nw workers from shifted sums
+template <class Fn>
+__device__ double lane_tree(Fn f, int m, int base, int c)
+{
+    if (c <= TREE_C) return lane_tree16(f, m, base, c);
+    // more terms than registers: subtrees of TREE_C terms merged in order by a binary counter
+    // (a new subtree is added to the pending one of its own height, lower half first)
+    double stk[12];
+    int lvl[12], sp = 0;
+    for (int b = 0; b < c; b += TREE_C) {
+        double v = lane_tree16(f, m, base + b, TREE_C);
+        int L = 0;
+        while (sp > 0 && lvl[sp - 1] == L) { v = stk[--sp] + v; ++L; }
+        stk[sp] = v; lvl[sp] = L; ++sp;
+    }
+    return stk[0];
+}
+
+// the whole wave: the tree over f(0 .. m), in every lane that holds terms
+template <class Fn>
+__device__ double wave_pairwise(Fn f, int m)
+{
+    int p = 1;
+    while (p < m) p <<= 1;
+    const int lanes = p > 64 ? 64 : p, c = p > 64 ? p / 64 : 1;
+    const int lane = threadIdx.x & 63;
+    double v = lane < lanes ? lane_tree(f, m, lane * c, c) : 0.0;
+    for (int o = 1; o < lanes; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Gelman-Rubin R-hat (Eq. 3) of one observable over nw workers from the shifted sums S1, S2
+// of n samples; the whole wave calls it, the value is valid in lane 0
 template <class F1, class F2>
-__device__ double rhat_dev(int nw, long long n, F1 s1, F2 s2)
+__device__ double rhat_wave(int nw, long long n, F1 s1, F2 s2)
 {
     const double dn = (double)n, dw = (double)nw;
-    const double m1 = pairwise_sum(nw, [&](int k) { return s1(k) / dn; }) / dw;
-    const double m2 = pairwise_sum(nw, [&](int k) { return s2(k) / dn; }) / dw;
-    const double m1sq = m1 * m1;
-    const double num = m2 - m1sq;
-    const double den = pairwise_sum(nw, [&](int k) {
+    const double m1 = wave_pairwise([&](int k) { return s1(k) / dn; }, nw) / dw;
+    const double m2 = wave_pairwise([&](int k) { return s2(k) / dn; }, nw) / dw;
+    const double den = wave_pairwise([&](int k) {
         const double ob = s1(k) / dn;
         const double a = s2(k) / dn;
         const double o2 = ob * ob;
         return a - o2;
-    }) / dw;
+    }, nw) / dw;
+    const double m1sq = m1 * m1;
+    const double num = m2 - m1sq;
     return den > 0.0 ? num / den : __longlong_as_double(0x7FF0000000000000LL);
 }
 
-// Fleming-Viot plan: survivors S (ascending), each exited worker r copies S[(u |S|) >> 32]
-// with u the first Philox word of (0, s, r, stream 2); -2 everywhere if S is empty.
+// Survivors of a check (Sec. 2.4.1): the workers r >= 1 not exited, ascending, into surv[];
+// returns their number.  Block-collective (blockDim a multiple of 64); wsum: LDS int[16].
 template <class Ex>
-__device__ void fv_plan_dev(uint32_t k0, uint32_t k1, long long s, int R, Ex exited, int *donor, int *surv)
+__device__ int survivors_block(int R, Ex exited, int *surv, int *wsum)
 {
-    int ns = 0;
-    for (int r = 1; r < R; ++r) if (!exited(r)) surv[ns++] = r;
-    donor[0] = ns == 0 ? -2 : -1;
-    for (int r = 1; r < R; ++r) {
-        if (ns == 0) { donor[r] = -2; continue; }
-        if (!exited(r)) { donor[r] = -1; continue; }
-        const uint4 w = philox_ctr(0u, s, (uint32_t)r, STREAM_BRANCH, k0, k1);
-        const unsigned long long pick = ((unsigned long long)w.x * (unsigned long long)ns) >> 32;
-        donor[r] = surv[pick];
+    const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wv = tid >> 6, nwv = nthr >> 6;
+    int run = 0;
+    for (int base = 1; base < R; base += nthr) {
+        const int r = base + tid;
+        const bool f = r < R && !exited(r);
+        const unsigned long long m = __ballot(f);
+        const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+        if (lane == 0) wsum[wv] = __popcll(m);
+        __syncthreads();
+        int off = run, tot = 0;
+        for (int k = 0; k < nwv; ++k) {
+            off += k < wv ? wsum[k] : 0;
+            tot += wsum[k];
+        }
+        if (f) surv[off + pre] = r;
+        run += tot;
+        __syncthreads();
     }
+    return run;
 }
 
-// Exit vote of Eq. 5 on first-exit check indices
-__device__ void vote_dev(int R, const long long *fec, long long t_check, long long *M, int *k, long long *tau)
+// Fleming-Viot donor of worker r at the check of global step s (Sec. 2.4.1): -1 for a
+// survivor, S[(u |S|) >> 32] for an exited worker (u the first Philox word of (0, s, r,
+// stream 2), S the ascending survivors, ns = |S|), -2 for every worker when no worker
+// survived; replica 0 (the reference walker) is never branched: -1, or -2 with no survivor.
+template <class Ex>
+__device__ __forceinline__ int fv_donor(uint32_t k0, uint32_t k1, long long s, int r, Ex exited, const int *surv, int ns)
 {
-    long long best = 0;
-    int kk = 0;
-    for (int r = 0; r < R; ++r) {
-        if (fec[r] <= 0) continue;
-        if (best == 0 || fec[r] < best) { best = fec[r]; kk = r + 1; }
-    }
-    *M = best;
-    *k = kk;
-    *tau = best > 0 ? ((long long)R * (best - 1) + kk) * t_check : 0;
+    if (ns == 0) return -2;
+    if (r == 0 || !exited(r)) return -1;
+    const uint4 w = philox_ctr(0u, s, (uint32_t)r, STREAM_BRANCH, k0, k1);
+    const unsigned long long pick = ((unsigned long long)w.x * (unsigned long long)ns) >> 32;
+    return surv[pick];
 }
 
-// Per-check bookkeeping (one workgroup).  mode: CHK_STATE (decorrelation: report replica 0),
-// CHK_DEPHASE (reference-exit test, branching plan into donor[], R-hat over workers with the
-// planned clones' sums), CHK_PARALLEL (first exiting replica), CHK_ADVANCE (record first
-// exit checks, R-hat computed and reported, nothing acted on).
-__global__ void __launch_bounds__(64) k_check(const Dev *__restrict__ Sp, int mode, long long s, int omega, int nrep, long long nsamp,
-                                              int check_index, Status *st, int *donor, int *surv, long long *fec)
+// Exit vote of Eq. 5 on first-exit check indices (0: no exit): M = the smallest positive
+// fec, k = 1 + the smallest r with fec[r] = M, tau = (R (M - 1) + k) t_check; (0, 0, 0) when
+// no replica exited.  Block-collective; the result is valid in thread 0.  red: LDS long long[32].
+template <class Fec>
+__device__ void vote_block(int R, Fec fec, long long t_check, long long *red, long long *M, int *k, long long *tau)
+{
+    const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wv = tid >> 6, nwv = nthr >> 6;
+    // key = (fec, r) ordered lexicographically; no exit is the largest key
+    long long bf = 0x7FFFFFFFFFFFFFFFLL;
+    int br = 0x7FFFFFFF;
+    for (int r = tid; r < R; r += nthr) {
+        const long long f = fec(r);
+        if (f > 0 && (f < bf || (f == bf && r < br))) { bf = f; br = r; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const long long of = __shfl_xor(bf, o, 64);
+        const int orr = __shfl_xor(br, o, 64);
+        if (of < bf || (of == bf && orr < br)) { bf = of; br = orr; }
+    }
+    if (lane == 0) { red[2 * wv] = bf; red[2 * wv + 1] = br; }
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < nwv; ++w) {
+            const long long of = red[2 * w];
+            const int orr = (int)red[2 * w + 1];
+            if (of < bf || (of == bf && orr < br)) { bf = of; br = orr; }
+        }
+        if (bf == 0x7FFFFFFFFFFFFFFFLL) { *M = 0; *k = 0; *tau = 0; }
+        else { *M = bf; *k = br + 1; *tau = ((long long)R * (bf - 1) + (br + 1)) * t_check; }
+    }
+    __syncthreads();
+}
+
+// Per-check bookkeeping and Fleming-Viot clone-on-kill in one launch; blocks of 256
+// threads, grid (nx, ny).  Block (0, 0) writes the status: CHK_STATE reports replica 0's
+// state; CHK_DEPHASE takes the reference-exit test, the branching plan (donor[], surv[])
+// and R-hat over the workers with the sums they hold after this check's branching;
+// CHK_PARALLEL records the replicas outside Omega at check `check_index` and takes the exit
+// vote of Eq. 5 (M, k, tau; to_state of replica k - 1); CHK_ADVANCE records first exit
+// checks in fec[] and computes, but does not act on, the plan and R-hat.  With CHK_DEPHASE
+// the blocks of row y = r (ny = R) copy (x, v, F) of replica r's donor into replica r when
+// r was killed (a slice of nx blocks each), mark r for a pair-list rebuild and copy the
+// donor's observable sums (cleared when every worker is re-copied from the reference).
+__global__ void __launch_bounds__(256) k_check(const Dev *__restrict__ Sp, int mode, long long s, int omega, int nrep,
+                                               long long nsamp, long long check_index, long long t_check, Status *st,
+                                               int *donor, int *surv, long long *fec)
 {
     const Dev &S = *Sp;
     const int tid = threadIdx.x;
-    __shared__ int no_surv;
+    const int r = blockIdx.y;
+    __shared__ int wsum[16];
+    __shared__ long long red[32];
+    __shared__ int sh_ne;
+    const int *state = S.state;
+    auto ex = [&](int q) { return state[q] != omega; };
+    const bool head = blockIdx.x == 0 && r == 0;
+    if (mode == CHK_DEPHASE) {
+        if (state[0] != omega) {
+            // the reference walker left Omega: nothing is branched
+            if (head && tid == 0) {
+                st->mode = mode; st->ref_exited = 1; st->n_exited = 0; st->n_surv = 0; st->k = 0;
+                st->M = 0; st->tau = 0; st->to_state = state[0];
+                for (int e = 0; e < 4; ++e) st->err[e] = S.err[e];
+                for (int j = 0; j < MAX_OBS; ++j) st->rhat[j] = __longlong_as_double(0x7FF0000000000000LL);
+            }
+            return;
+        }
+        if (!head && (r == 0 || !ex(r))) return;          // survivors are never copied
+    } else if (!head) {
+        return;
+    }
+    // survivors (every block that needs a donor): into the global list from block (0, 0),
+    // into LDS elsewhere
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    int *sl = head ? surv : (int *)lds_raw;
+    const int ns = survivors_block(nrep, ex, sl, wsum);
+    if (!head) {
+        // an exited worker: copy its donor (the reference walker when no worker survived)
+        __syncthreads();
+        const int d = ns == 0 ? 0 : fv_donor(S.key0, S.key1, s, r, ex, sl, ns);
+        const size_t bs = (size_t)d * 3 * S.np, bd = (size_t)r * 3 * S.np;
+        for (int k = blockIdx.x * blockDim.x + tid; k < 3 * S.np; k += gridDim.x * blockDim.x) {
+            S.x[bd + k] = S.x[bs + k];
+            S.v[bd + k] = S.v[bs + k];
+            S.F[bd + k] = S.F[bs + k];
+        }
+        if (blockIdx.x == 0 && tid == 0) S.need_build[r] = 1;
+        if (blockIdx.x == 0 && tid < 2 * MAX_OBS)
+            S.acc[(size_t)r * 2 * MAX_OBS + tid] = d == 0 ? 0.0 : S.acc[(size_t)d * 2 * MAX_OBS + tid];
+        return;
+    }
+    // block (0, 0): the plan, the status and R-hat
+    if (tid == 0) { sh_ne = 0; }
+    __syncthreads();
+    int ne = 0;
+    for (int q = tid; q < nrep; q += blockDim.x) {
+        const int dq = fv_donor(S.key0, S.key1, s, q, ex, sl, ns);
+        if (mode == CHK_DEPHASE || mode == CHK_ADVANCE) donor[q] = dq;
+        ne += q > 0 && ex(q);
+        if (mode == CHK_ADVANCE && fec[q] == 0 && ex(q)) fec[q] = check_index;
+    }
+    for (int o = 32; o > 0; o >>= 1) ne += __shfl_xor(ne, o, 64);
+    if ((tid & 63) == 0 && ne) atomicAdd(&sh_ne, ne);
+    long long vM = 0, vtau = 0;
+    int vk = 0;
+    if (mode == CHK_PARALLEL)
+        vote_block(nrep, [&](int q) { return ex(q) ? check_index : 0ll; }, t_check, red, &vM, &vk, &vtau);
+    __syncthreads();
     if (tid == 0) {
         st->mode = mode;
         st->ref_exited = 0;
-        st->n_exited = 0;
-        st->n_surv = 0;
-        st->k = 0;
-        st->to_state = S.state[0];
+        st->n_exited = (mode == CHK_DEPHASE || mode == CHK_ADVANCE) ? sh_ne : 0;
+        st->n_surv = (mode == CHK_DEPHASE || mode == CHK_ADVANCE) ? ns : 0;
+        st->k = vk;
+        st->M = vM;
+        st->tau = vtau;
+        st->to_state = state[vk > 0 ? vk - 1 : 0];
         for (int e = 0; e < 4; ++e) st->err[e] = S.err[e];
-        no_surv = 0;
-        if (mode == CHK_DEPHASE) {
-            if (S.state[0] != omega) {
-                st->ref_exited = 1;
-                for (int r = 0; r < nrep; ++r) donor[r] = -1;
-            } else {
-                auto ex = [&](int r) { return S.state[r] != omega; };
-                fv_plan_dev(S.key0, S.key1, s, nrep, ex, donor, surv);
-                int ne = 0;
-                for (int r = 1; r < nrep; ++r) ne += ex(r);
-                st->n_exited = ne;
-                st->n_surv = nrep - 1 - ne;
-                if (nrep > 1 && donor[1] == -2) {
-                    no_surv = 1;
-                    donor[0] = -1;
-                    for (int r = 1; r < nrep; ++r) donor[r] = 0;   // re-copy every worker from the reference
-                }
-            }
-        } else if (mode == CHK_PARALLEL) {
-            for (int r = 0; r < nrep; ++r)
-                if (S.state[r] != omega) { st->k = r + 1; st->to_state = S.state[r]; break; }
-        } else if (mode == CHK_ADVANCE) {
-            // first exit checks for the vote, and the branching plan of this check (reported,
-            // not acted on)
-            auto ex = [&](int r) { return S.state[r] != omega; };
-            int ne = 0;
-            for (int r = 0; r < nrep; ++r) {
-                if (fec[r] == 0 && ex(r)) fec[r] = check_index;
-                ne += r > 0 && ex(r);
-            }
-            fv_plan_dev(S.key0, S.key1, s, nrep, ex, donor, surv);
-            st->n_exited = ne;
-            st->n_surv = nrep - 1 - ne;
-        }
     }
-    __syncthreads();
-    if ((mode == CHK_DEPHASE || mode == CHK_ADVANCE) && tid < MAX_OBS) {
-        double rh = __longlong_as_double(0x7FF0000000000000LL);
-        const bool skip = (mode == CHK_DEPHASE && no_surv) || nsamp < 1 || tid >= S.nobs;
-        if (!skip) {
-            const int j = tid;
-            auto src = [&](int k) {
-                int r = k + 1;
-                if (mode == CHK_DEPHASE && donor[r] >= 0) r = donor[r];
-                return r;
-            };   // the sums a worker holds after this check's branching
-            auto s1 = [&](int k) { return S.acc[((size_t)src(k) * MAX_OBS + j) * 2]; };
-            auto s2 = [&](int k) { return S.acc[((size_t)src(k) * MAX_OBS + j) * 2 + 1]; };
-            rh = rhat_dev(nrep - 1, nsamp, s1, s2);
+    if (mode == CHK_DEPHASE || mode == CHK_ADVANCE) {
+        // one wave per observable; after this check's branching a killed worker holds its
+        // donor's sums, and with no survivor every worker restarts (R-hat undefined)
+        const int wv = tid >> 6, nwv = blockDim.x >> 6;
+        for (int j = wv; j < MAX_OBS; j += nwv) {
+            double rh = __longlong_as_double(0x7FF0000000000000LL);
+            const bool skip = (mode == CHK_DEPHASE && ns == 0) || nsamp < 1 || j >= S.nobs;
+            if (!skip) {
+                auto src = [&](int k) {
+                    const int q = k + 1;
+                    return (mode == CHK_DEPHASE && donor[q] >= 0) ? donor[q] : q;
+                };
+                auto s1 = [&](int k) { return S.acc[((size_t)src(k) * MAX_OBS + j) * 2]; };
+                auto s2 = [&](int k) { return S.acc[((size_t)src(k) * MAX_OBS + j) * 2 + 1]; };
+                rh = rhat_wave(nrep - 1, nsamp, s1, s2);
+            }
+            if ((tid & 63) == 0) st->rhat[j] = rh;
         }
-        st->rhat[tid] = rh;
     }
 }
 
@@ -1724,31 +1837,35 @@ __global__ void __launch_bounds__(256) k_noise_test(uint32_t k0, uint32_t k1, in
     gauss[3 * a] = g.x; gauss[3 * a + 1] = g.y; gauss[3 * a + 2] = g.z;
 }
 
-__global__ void k_fvplan_test(uint32_t k0, uint32_t k1, long long s, int R, const uint8_t *exited, int *donor, int *surv)
+// the branching plan of one check, by the routines k_check runs (one block of 256 threads)
+__global__ void __launch_bounds__(256) k_fvplan_test(uint32_t k0, uint32_t k1, long long s, int R, const uint8_t *exited,
+                                                     int *donor, int *surv)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        auto ex = [&](int r) { return exited[r] != 0; };
-        fv_plan_dev(k0, k1, s, R, ex, donor, surv);
-    }
+    __shared__ int wsum[16];
+    auto ex = [&](int r) { return exited[r] != 0; };
+    const int ns = survivors_block(R, ex, surv, wsum);
+    for (int r = threadIdx.x; r < R; r += blockDim.x) donor[r] = fv_donor(k0, k1, s, r, ex, surv, ns);
 }
 
-__global__ void k_rhat_test(int nw, int nobs, long long n, const double *S1, const double *S2, double *out)
+// R-hat of observable blockIdx.x, by the routine k_check runs (one wave per observable)
+__global__ void __launch_bounds__(64) k_rhat_test(int nw, int nobs, long long n, const double *S1, const double *S2,
+                                                  double *out)
 {
-    const int j = threadIdx.x;
-    if (j >= nobs) return;
+    const int j = blockIdx.x;
     auto s1 = [&](int k) { return S1[(size_t)k * nobs + j]; };
     auto s2 = [&](int k) { return S2[(size_t)k * nobs + j]; };
-    out[j] = rhat_dev(nw, n, s1, s2);
+    const double rh = rhat_wave(nw, n, s1, s2);
+    if (threadIdx.x == 0) out[j] = rh;
 }
 
-__global__ void k_vote_test(int R, const long long *fec, long long t_check, long long *out)
+// the exit vote of Eq. 5, by the routine k_check runs (one block of 256 threads)
+__global__ void __launch_bounds__(256) k_vote_test(int R, const long long *fec, long long t_check, long long *out)
 {
-    if (threadIdx.x == 0) {
-        long long M, tau;
-        int k;
-        vote_dev(R, fec, t_check, &M, &k, &tau);
-        out[0] = M; out[1] = k; out[2] = tau;
-    }
+    __shared__ long long red[32];
+    long long M, tau;
+    int k;
+    vote_block(R, [&](int r) { return fec[r]; }, t_check, red, &M, &k, &tau);
+    if (threadIdx.x == 0) { out[0] = M; out[1] = k; out[2] = tau; }
 }
 
 } // namespace gpr
