@@ -389,6 +389,16 @@ gpr_status gpr_philox_noise(uint64_t seed, int32_t replica, int64_t step, int32_
  * counter (0, s lo, r, 2 << 24 | s hi)), -1 for others; -2 everywhere if no survivor. */
 gpr_status gpr_fv_plan(uint64_t seed, int64_t step, int32_t R, const uint8_t *exited, int32_t *donor);
 
+/* gpr_fv_plan for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same arguments and results, but
+ * the exited flags, the survivor list and the donors are staged through one device array of
+ * the library, sized for R <= GPR_NOALLOC_MAX_R, that every device the library runs on holds
+ * until the process ends; the call allocates and frees no device memory.  EINVAL (nothing
+ * done) for R beyond the limit.  Calls on one device share that array: calls that overlap on
+ * a device (several host threads) race and must be serialised by the caller. */
+#define GPR_NOALLOC_MAX_R 16384
+gpr_status gpr_fv_plan_noalloc(uint64_t seed, int64_t step, int32_t R, const uint8_t *exited, int32_t *donor);
+
 /* Gelman-Rubin statistic (Eq. 3) over nw workers from shifted sums: Ob_k = S1[k]/n,
  * num = mean_k(S2[k]/n) - (mean_k Ob_k)^2, den = mean_k(S2[k]/n - Ob_k^2), rhat = num/den
  * (+inf if den <= 0).  Means are pairwise sums over k on one canonical tree: the nw terms

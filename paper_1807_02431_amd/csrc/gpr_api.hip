@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1822,6 +1823,58 @@ extern "C" gpr_status gpr_fv_plan(uint64_t seed, int64_t step, int32_t R, const 
     TMPCHK(tmp_alloc(t.v, &ex, R));
     TMPCHK(tmp_alloc(t.v, &dn, R));
     TMPCHK(tmp_alloc(t.v, &sv, R));
+    TMPCHK(hipMemcpy(ex, exited, R, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_fvplan_test, dim3(1), dim3(256), 0, 0, (uint32_t)seed, (uint32_t)(seed >> 32), (long long)step, R, ex, dn, sv);
+    TMPCHK(hipGetLastError());
+    TMPCHK(hipMemcpy(donor, dn, sizeof(int) * R, hipMemcpyDeviceToHost));
+    return GPR_OK;
+}
+
+// ------------------------------------------------------------------ branching plan without allocation
+// Device array that gpr_fv_plan_noalloc stages through, for up to GPR_NOALLOC_MAX_R replicas:
+// donors (int) at byte 0, the survivor list (int) at 4 * max, the exited flags at 8 * max.
+// Every device the library runs on holds its own copy until the process ends.  In host code
+// its name is not a device address: the address is taken per device with
+// hipGetSymbolAddress and only that address is used.
+constexpr size_t NOALLOC_BYTES = (size_t)9 * GPR_NOALLOC_MAX_R;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEV = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[NOALLOC_MAX_DEV] = {};
+
+// the device address of `scratch` on the current device, taken on the first call there
+hipError_t scratch_of_current_device(unsigned char **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEV) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = (unsigned char *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+} // namespace
+
+extern "C" gpr_status gpr_fv_plan_noalloc(uint64_t seed, int64_t step, int32_t R, const uint8_t *exited, int32_t *donor)
+{
+    if (R < 1 || !exited || !donor) return fail(nullptr, GPR_EINVAL, "bad arguments");
+    if (R > GPR_NOALLOC_MAX_R)
+        return fail(nullptr, GPR_EINVAL, "R exceeds GPR_NOALLOC_MAX_R (" + std::to_string(GPR_NOALLOC_MAX_R) + ")");
+    unsigned char *base = nullptr;
+    TMPCHK(scratch_of_current_device(&base));
+    int *dn = (int *)base;
+    int *sv = (int *)(base + (size_t)4 * GPR_NOALLOC_MAX_R);
+    uint8_t *ex = base + (size_t)8 * GPR_NOALLOC_MAX_R;
+    // every word the kernel reads is written first (flags copied in, survivors and donors
+    // written before they are read), so nothing needs clearing between calls
     TMPCHK(hipMemcpy(ex, exited, R, hipMemcpyHostToDevice));
     hipLaunchKernelGGL(k_fvplan_test, dim3(1), dim3(256), 0, 0, (uint32_t)seed, (uint32_t)(seed >> 32), (long long)step, R, ex, dn, sv);
     TMPCHK(hipGetLastError());

@@ -18,6 +18,7 @@ EINVAL, ENOMEM, EDEVICE, EPHASE, EUNSTABLE = -1, -2, -3, -4, -5
 PATH_PLAIN, PATH_PERSISTENT = 0, 1
 MAX_OBS = 8
 MAX_BOXES = 8
+NOALLOC_MAX_R = 16384     # GPR_NOALLOC_MAX_R: replicas gpr_fv_plan_noalloc takes
 
 
 class GprError(RuntimeError):
@@ -104,6 +105,7 @@ SIGNATURES = {
     "gpr_philox_noise": (C.c_int32, [C.c_uint64, C.c_int32, C.c_int64, C.c_int32, C.c_int32,
                                      C.POINTER(C.c_uint32), C.POINTER(C.c_float)]),
     "gpr_fv_plan": (C.c_int32, [C.c_uint64, C.c_int64, C.c_int32, C.POINTER(C.c_uint8), _PI]),
+    "gpr_fv_plan_noalloc": (C.c_int32, [C.c_uint64, C.c_int64, C.c_int32, C.POINTER(C.c_uint8), _PI]),
     "gpr_rhat": (C.c_int32, [C.c_int32, C.c_int32, C.c_int64, _PD, _PD, _PD]),
     "gpr_exit_vote": (C.c_int32, [C.c_int32, _P64, C.c_int64, _P64, C.POINTER(C.c_int32), _P64]),
     "gpr_dephase_fixed": (C.c_int32, [_VP, C.c_int64, C.c_int64, C.POINTER(_Dephase)]),
@@ -404,6 +406,15 @@ def fv_plan(seed, step, exited):
     donor = np.zeros(len(ex), np.int32)
     _check(lib().gpr_fv_plan(int(seed) & 0xFFFFFFFFFFFFFFFF, int(step), len(ex),
                              ex.ctypes.data_as(C.POINTER(C.c_uint8)), _pi(donor)))
+    return donor
+
+
+def fv_plan_noalloc(seed, step, exited):
+    """gpr_fv_plan staged through the library's static device array (no allocation)."""
+    ex = np.ascontiguousarray(exited, np.uint8)
+    donor = np.zeros(len(ex), np.int32)
+    _check(lib().gpr_fv_plan_noalloc(int(seed) & 0xFFFFFFFFFFFFFFFF, int(step), len(ex),
+                                     ex.ctypes.data_as(C.POINTER(C.c_uint8)), _pi(donor)))
     return donor
 
 
