@@ -9,6 +9,10 @@ and every t_check = 1000 steps the state test of every replica, the Fleming-Viot
 branching plan, the Gelman-Rubin statistics and the exit vote (computed, not acted on, so
 that the work per step is fixed).
 
+The samples and checks that fall inside the timed steps are reported ("window"); the schedule
+runs on the steps of all calls, so a short timed window may hold none, and the latency of a call
+that ends at a check is measured on its own ("check_latency").
+
 The product path (persistent kernel) is timed, then the plain one-launch-per-kernel-per-step
 path on the same system and seeds, launched from the host and replayed from a HIP graph.  Prints one JSON line.
 `value` comes from the first timed run of --steps steps; both paths are then timed --repeats - 1
@@ -75,22 +79,36 @@ def kernel_source_hash():
 
 def _profile_figure(fname, key, steps_per_launch):
     """A per-launch figure of the persistent kernel from a committed rocprofv3 summary, or None
-    when the kernel sources (or the compiler flags) or the launch length differ from the ones
-    the counters were taken on."""
+    when the kernel sources (or the compiler flags) differ from the ones the counters were
+    taken on.  The summary lists the figure for each launch length it measured
+    (``<key>_<steps> <value>``); a launch of another length gets the straight line a + b L
+    through the two measured lengths nearest to it (a: the work of a launch's start and end,
+    b: the work of one step)."""
     path = os.path.join(ROOT, "profiles", fname)
     if not os.path.exists(path):
         return None
-    kv = {}
+    kv, pts = {}, {}
     with open(path) as fh:
         for line in fh:
             parts = line.split()
-            if len(parts) == 2:
-                kv[parts[0]] = parts[1]
-    try:
-        ok = kv["source_sha256"] == kernel_source_hash() and int(kv["steps_per_launch"]) == int(round(steps_per_launch))
-        return int(kv[key]) if ok else None
-    except (KeyError, ValueError):
+            if len(parts) != 2:
+                continue
+            kv[parts[0]] = parts[1]
+            if parts[0].startswith(key + "_"):
+                try:
+                    pts[int(parts[0][len(key) + 1:])] = float(parts[1])
+                except ValueError:
+                    pass
+    if kv.get("source_sha256") != kernel_source_hash() or not pts:
         return None
+    L = float(steps_per_launch)
+    if int(round(L)) in pts:
+        return pts[int(round(L))]
+    if len(pts) < 2:
+        return None
+    (l0, v0), (l1, v1) = sorted(sorted(pts.items(), key=lambda kv_: abs(kv_[0] - L))[:2])
+    b = (v1 - v0) / (l1 - l0)
+    return v0 + b * (L - l0)
 
 
 def measured_traffic(steps_per_launch):
@@ -101,6 +119,12 @@ def measured_traffic(steps_per_launch):
 def measured_fp32_flop(steps_per_launch):
     """FP32 FLOP executed per launch (rocprofv3 SQ_INSTS_VALU_{ADD,MUL,TRANS,FMA}_F32)."""
     return _profile_figure("k_persist_rl2432x64_valu_counters.md", "fp32_flop_per_launch", steps_per_launch)
+
+
+def window_counts(t0, t1, t_gr, t_check):
+    """Observable samples and exit checks that fall in the steps (t0, t1] of gpr_advance's
+    schedule (samples every t_GR, checks every t_check, counted over all calls)."""
+    return dict(samples=t1 // t_gr - t0 // t_gr, checks=t1 // t_check - t0 // t_check)
 
 
 def flops_per_replica_step(spec, pairs):
@@ -209,9 +233,93 @@ def differentiation_bench(spec, iters):
         once()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / iters
+    s.close()
     return dict(batch_evals_per_s=1.0 / dt, replica_evals_per_s=R / dt, ms_per_batch_eval=1e3 * dt,
                 iters=iters, note="forward = energies + forces of all replicas (pair lists rebuilt); "
                 "backward = dU/dx and dU/d(eps, sigma, q, torsion k) summed over replicas")
+
+
+def pair_kernel_bench(pl, spec, pairs, launches=100):
+    """The plain path's pair-force kernel (k_nonbonded, all replicas in one launch) timed launch
+    by launch with HIP events over one-step calls; the median is a step without a pair-list
+    rebuild (the lists are rebuilt on one step in ten).  Its algorithmic rate counts each
+    in-cutoff unordered pair once at FLOP_PAIR."""
+    R = spec["n_replicas"]
+    pl.profile(True)
+    prev_ms, prev_n = pl.profile_read()
+    per = []
+    for _ in range(launches):
+        pl.advance(1)
+        ms, n_ = pl.profile_read()
+        if n_ > prev_n:
+            per.append((ms - prev_ms) / (n_ - prev_n))
+        prev_ms, prev_n = ms, n_
+    pl.profile(False)
+    # launches in which some replica rebuilds its lists (period or displacement guard) take
+    # about twice as long; the median of the faster cluster is the pair loop alone
+    cut = 0.5 * (min(per) + max(per))
+    fast = [x for x in per if x <= cut]
+    med = float(np.median(fast)) * 1e-3
+    achieved = pairs * FLOP_PAIR * R / med / 1e12
+    return dict(kernel="k_nonbonded", launches=len(per), launches_without_rebuild=len(fast), median_us=med * 1e6,
+                median_all_us=1e3 * float(np.median(per)), max_us=1e3 * max(per), min_us=1e3 * min(per),
+                achieved_tflops=achieved, frac=achieved / PEAK_FP32_TFLOPS,
+                note="plain path, one launch for all 64 replicas; median of the launches without a pair-list "
+                     "rebuild (those below the midpoint of the fastest and slowest launch); full per-atom lists: "
+                     "each in-cutoff pair is evaluated twice and counted once")
+
+
+def check_latency_bench(sysobj, t_check, checks=4):
+    """Wall time of the one-step call that ends at an exit check (state test, branching plan,
+    R-hat, exit vote, status read back) less that of an ordinary one-step call."""
+    import torch
+
+    def one():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sysobj.advance(1)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+    at, plain = [], []
+    for _ in range(checks):
+        left = (-sysobj.advance_steps() - 1) % t_check
+        if left:
+            sysobj.advance(left)
+        at.append(one())
+        plain.append(one())
+    return dict(us=1e6 * (float(np.median(at)) - float(np.median(plain))),
+                call_at_check_us=1e6 * float(np.median(at)), call_without_check_us=1e6 * float(np.median(plain)),
+                checks=checks)
+
+
+def small_configs_bench(seconds=2.0):
+    """The toy (8 replicas) and the 22-atom chain (256 replicas) on the persistent path,
+    each beside the oracle on one host core for about ``seconds`` of steps."""
+    import torch
+    import gpr_synth as G
+    import oracle
+    import paper_1807_02431_amd as gpr
+    out = {}
+    for name, steps in (("toy", 20000), ("chain22", 5000)):
+        spec = G.config(name)
+        R = spec["n_replicas"]
+        g = gpr.System(spec, path=gpr.PATH_PERSISTENT, stream=torch.cuda.current_stream())
+        g.advance(steps // 10)
+        t = timed_advance(g, steps)
+        g.close()
+        o = oracle.System(spec)
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < seconds:
+            o.advance(10)
+            k += 10
+        to = time.perf_counter() - t0
+        out[name] = dict(n_atoms=spec["n_atoms"], n_replicas=R, steps=steps,
+                         replica_steps_per_s=R * steps / t, atom_steps_per_s=R * spec["n_atoms"] * steps / t,
+                         t_gr=spec["t_gr"], t_check=spec["t_check_dephase"],
+                         cpu_baseline=dict(value=R * k / to, unit="replica-steps/s", cores=1, kind="oracle",
+                                           sample="%d replicas x %d steps (FP64)" % (R, k)))
+    return out
 
 
 def batching_bench(steps):
@@ -237,6 +345,8 @@ def batching_bench(steps):
         x.advance(steps)
     torch.cuda.synchronize()
     ts = time.perf_counter() - t0
+    for x in batch + solo:
+        x.close()
     reps = sum(s["n_replicas"] for s in specs)
     atoms = sum(s["n_replicas"] * s["n_atoms"] for s in specs)
     return dict(systems="22, 300, 1200, 2432 atoms x 192 replicas each", replicas=reps, steps=steps,
@@ -255,6 +365,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven multi-system batching measurement")
+    ap.add_argument("--no-small", action="store_true", help="skip the toy and 22-atom chain measurements")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 256 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -292,16 +403,20 @@ def main():
     ps.advance(args.warmup)
     ps.profile(True)
     print("# persistent path: timing %d steps" % args.steps, file=sys.stderr, flush=True)
+    a0 = ps.advance_steps()
     t_p = timed_advance(ps, args.steps)
+    window = window_counts(a0, ps.advance_steps(), spec["t_gr"], spec["t_check_dephase"])
     kms, klaunch = ps.profile_read()
     ps.profile(False)
     reps_p = [t_p] + [timed_advance(ps, args.steps) for _ in range(args.repeats - 1)]
     q_samples = [ps.get_state(r)[0] for r in (0, R // 2, R - 1)]
     pairs = float(np.mean([in_cutoff_pairs(spec, q) for q in q_samples]))
     frs = flops_per_replica_step(spec, pairs)
+    print("# persistent path: latency of an exit check", file=sys.stderr, flush=True)
+    check_lat = check_latency_bench(ps, spec["t_check_dephase"])
 
     # ------------------------------------------------------------ plain path
-    plain = plain_graph = None
+    plain = plain_graph = k1 = None
     if not args.no_plain:
         print("# plain path: warmup %d, timing %d steps" % (args.warmup, args.steps), file=sys.stderr, flush=True)
         pl = gpr.System(spec, path=gpr.PATH_PLAIN, stream=stream)
@@ -316,6 +431,9 @@ def main():
                      ms_per_step=1e3 * t_pl / args.steps, launches_per_step=3,
                      median_ms_per_step=1e3 * float(np.median(reps_pl)) / args.steps,
                      pair_kernel_us=1e3 * nb_ms / max(nb_n, 1))
+        print("# plain path: pair-force kernel launch by launch", file=sys.stderr, flush=True)
+        k1 = pair_kernel_bench(pl, spec, pairs)
+        pl.close()
         print("# plain path replayed from a HIP graph: warmup %d, timing %d steps" % (args.warmup, args.steps),
               file=sys.stderr, flush=True)
         pg = gpr.System(spec, path=gpr.PATH_PLAIN, stream=stream)
@@ -324,6 +442,7 @@ def main():
         t_pg = timed_advance(pg, args.steps)
         plain_graph = dict(replica_steps_per_s=R * args.steps / t_pg, ms_per_step=1e3 * t_pg / args.steps,
                            cycle_steps=GRAPH_CYCLE)
+        pg.close()
 
     diff = None
     if not args.no_diff:
@@ -334,6 +453,11 @@ def main():
     if not args.no_batch:
         print("# uneven multi-system batching", file=sys.stderr, flush=True)
         batching = batching_bench(1000)
+
+    small = None
+    if not args.no_small:
+        print("# toy and 22-atom chain", file=sys.stderr, flush=True)
+        small = small_configs_bench()
 
     cpu = None if args.no_cpu else cpu_baseline(spec)
     if cpu is not None:
@@ -354,6 +478,9 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": 1e3 * t_p / args.steps,
+        "window": dict(window, note="observable samples (every t_GR = 50) and exit checks (every t_check = "
+                                    "1,000) of the product schedule inside the timed steps"),
+        "check_latency": check_lat,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -376,10 +503,17 @@ def main():
                      "kernel": "k_persist", "avg_launch_us": avg_launch_s * 1e6,
                      "steps_per_launch": steps_per_launch, "flop_per_replica_step": frs,
                      "in_cutoff_pairs_per_replica": pairs},
+        "pair_kernel": k1,
         "cpu_baseline": cpu,
         "differentiation": diff,
         "batching": batching,
+        "small_configs": small,
     }
+    # handles destroyed before the interpreter ends (device buffers, events, pinned memory)
+    ps.close()
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
 
 

@@ -347,6 +347,10 @@ gpr_status gpr_set_state(gpr_system *sys, int32_t r, const double *q, const doub
  * state != Omega (0 if none).  The fixed-work stepping loop of the measurement harness. */
 gpr_status gpr_advance(gpr_system *sys, int64_t nsteps, int64_t *first_exit_check);
 
+/* Steps taken by gpr_advance / gpr_batch_advance on the handle since creation (the position
+ * in their sampling and check schedule); -1 for a NULL handle. */
+int64_t gpr_advance_steps(const gpr_system *sys);
+
 /* gpr_advance of several systems (1 to 8, each its own handle, all on one stream and able to
  * use the persistent path) whose persistent steps share launches: each launch advances every
  * system up to the next exit check of any of them (their t_check_dephase may differ), the

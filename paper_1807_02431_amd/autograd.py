@@ -56,6 +56,9 @@ class _Energy(torch.autograd.Function):
         model.system.energy_forces_dev(x32.data_ptr(), U.data_ptr(), 0)
         model._gen += 1
         ctx.model, ctx.gen, ctx.x_dtype = model, model._gen, x.dtype
+        # the parameters this pass used (host copies, owned by the pass): a later pass with
+        # other parameters must not change what this pass's backward differentiates
+        ctx.params = tuple(a.copy() for a in model._params)
         ctx.save_for_backward(x32)
         return U
 
@@ -64,7 +67,12 @@ class _Energy(torch.autograd.Function):
         model = ctx.model
         x32, = ctx.saved_tensors
         g = gU.detach().to(torch.float64).contiguous()
-        if model._gen != ctx.gen:
+        stale_params = not all(np.array_equal(a, b) for a, b in zip(ctx.params, model._params))
+        if stale_params:
+            # a later forward pass changed the parameters: put this pass's back
+            model.system.set_params(*ctx.params)
+            model._params = tuple(a.copy() for a in ctx.params)
+        if model._gen != ctx.gen or stale_params:
             # a later forward pass moved the replicas: put this pass's positions (and forces) back
             model.system.energy_forces_dev(x32.data_ptr(), 0, 0)
             model._gen += 1

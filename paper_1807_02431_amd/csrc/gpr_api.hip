@@ -1195,6 +1195,7 @@ extern "C" double gpr_simulated_time(const gpr_system *S) { return S ? (double)S
 extern "C" int64_t gpr_simulated_steps(const gpr_system *S) { return S ? S->tsim : -1; }
 extern "C" int64_t gpr_global_step(const gpr_system *S) { return S ? S->s : -1; }
 extern "C" int32_t gpr_current_state(const gpr_system *S) { return S ? S->omega : INT32_MIN; }
+extern "C" int64_t gpr_advance_steps(const gpr_system *S) { return S ? S->adv_t : -1; }
 
 extern "C" gpr_status gpr_energy_forces(gpr_system *S, int32_t r0, int32_t nr, double *energy, double *forces)
 {

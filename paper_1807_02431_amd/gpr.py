@@ -95,6 +95,7 @@ SIGNATURES = {
     "gpr_simulated_steps": (C.c_int64, [_VP]),
     "gpr_global_step": (C.c_int64, [_VP]),
     "gpr_current_state": (C.c_int32, [_VP]),
+    "gpr_advance_steps": (C.c_int64, [_VP]),
     "gpr_get_state": (C.c_int32, [_VP, C.c_int32, _PD, _PD]),
     "gpr_set_state": (C.c_int32, [_VP, C.c_int32, _PD, _PD]),
     "gpr_advance": (C.c_int32, [_VP, C.c_int64, _P64]),
@@ -375,6 +376,10 @@ class System:
         o = _Exit()
         rc = self._c(lib().gpr_parallel_step(self._h, int(max_checks), C.byref(o)))
         return rc, dict(M=o.M, k=o.k, to_state=o.to_state, tau_steps=o.tau_steps, tau=o.tau)
+
+    def advance_steps(self):
+        """Steps taken by advance / batch_advance since creation (their schedule's position)."""
+        return lib().gpr_advance_steps(self._h)
 
     def advance(self, nsteps):
         fec = np.zeros(self.R, np.int64)

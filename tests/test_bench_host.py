@@ -1,6 +1,7 @@
 """Host logic of bench.py (CPU): the in-cutoff pair count behind the roofline's algorithmic
 FLOP figure against a brute-force count, the stored HBM traffic figure offered only for the
-kernel sources and launch length it was measured on, and the one-GPU guard."""
+kernel sources it was measured on (and interpolated between measured launch lengths), the
+samples and checks counted in a timed window, and the one-GPU guard."""
 import os
 import subprocess
 import sys
@@ -45,18 +46,34 @@ def test_flop_count_adds_up():
                     + len(spec["pairs14"]) * bench.FLOP_PAIR14 + spec["n_atoms"] * bench.FLOP_ATOM_BAOAB)
 
 
-def test_traffic_only_for_the_profiled_kernel_and_launch_length(tmp_path, monkeypatch):
+def test_traffic_only_for_the_profiled_kernel_sources(tmp_path, monkeypatch):
+    """A stored per-launch figure is offered only for the kernel sources it was measured on;
+    for a launch length it was measured at it is returned as stored, for another length from
+    the straight line through the two nearest measured lengths, and with one length only for
+    that length."""
     sha = bench.kernel_source_hash()
     prof = tmp_path / "profiles"
     prof.mkdir()
     f = prof / "k_persist_rl2432x64_hbm_traffic.md"
-    f.write_text("machine-readable:\nsource_sha256 %s\nsteps_per_launch 1000\nhbm_bytes_per_launch 12345\n" % sha)
+    f.write_text("machine-readable:\nsource_sha256 %s\nhbm_bytes_per_launch_1000 12345\n" % sha)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: sha)
     assert bench.measured_traffic(1000) == 12345
     assert bench.measured_traffic(500) is None
+    f.write_text("machine-readable:\nsource_sha256 %s\nhbm_bytes_per_launch_20 3000\n"
+                 "hbm_bytes_per_launch_1000 101000\n" % sha)
+    assert bench.measured_traffic(20) == 3000
+    assert bench.measured_traffic(1000) == 101000
+    assert bench.measured_traffic(500) == pytest.approx(3000 + 100 * 480)
+    assert bench.measured_traffic(2000) == pytest.approx(3000 + 100 * 1980)
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 64)
     assert bench.measured_traffic(1000) is None
+
+
+def test_window_counts():
+    assert bench.window_counts(5, 25, 50, 1000) == dict(samples=0, checks=0)
+    assert bench.window_counts(1000, 11000, 50, 1000) == dict(samples=200, checks=10)
+    assert bench.window_counts(990, 1010, 50, 1000) == dict(samples=1, checks=1)
 
 
 def test_kernel_hash_covers_sources_and_flags():

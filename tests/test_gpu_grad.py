@@ -137,3 +137,34 @@ def test_parameters_change_the_dynamics_consistently():
     g.advance(10)
     with pytest.raises(gpr.GprError):
         g.set_params(epsilon=-np.ones(spec["n_atoms"]))
+
+
+def test_backward_of_an_earlier_pass_uses_its_own_parameters():
+    """forward(p1), forward(p2), then the backward of the first pass: its gradients are those
+    of p1 at the first pass's positions (oracle gradient at p1), not of the later p2."""
+    import torch
+    from paper_1807_02431_amd.autograd import EnergyModel
+    spec = G.round_to_f32(G.config("rl300", n_replicas=4))
+    model = EnergyModel(spec)
+    eps, sig, chg, tk = [t.requires_grad_() for t in model.parameters()]
+    X = np.stack([np.asarray(spec["pos"], np.float32)] * 4)
+    X[1:] += np.random.default_rng(3).normal(scale=0.01, size=X[1:].shape).astype(np.float32)
+    x1 = torch.tensor(X, device="cuda", requires_grad=True)
+    U1 = model(x1, eps, sig, chg, tk)
+    eps2 = (eps.detach() * 1.3).requires_grad_()
+    chg2 = (chg.detach() * 0.7).requires_grad_()
+    x2 = torch.tensor(X * 1.001, device="cuda", requires_grad=True)
+    U2 = model(x2, eps2, sig, chg2, tk)
+    U1.sum().backward()
+    ref = _oracle_weighted(spec, X.astype(np.float64), np.ones(4))
+    for key, t in (("epsilon", eps), ("sigma", sig), ("charge", chg), ("torsion_k", tk)):
+        assert _rel(t.grad.cpu().numpy(), ref[key]) < 1e-4, key
+    o = oracle.System(dict(spec, n_replicas=2))
+    for r in range(4):
+        assert _rel(x1.grad[r].cpu().numpy(), -o.eval(X[r])[1]) < 1e-5
+    # and the second pass, run backward afterwards, still gets p2's gradient
+    U2.sum().backward()
+    spec2 = dict(spec, epsilon=np.asarray(spec["epsilon"]) * 1.3, charge=np.asarray(spec["charge"]) * 0.7)
+    ref2 = _oracle_weighted(spec2, (X * 1.001).astype(np.float32).astype(np.float64), np.ones(4))
+    assert _rel(eps2.grad.cpu().numpy(), ref2["epsilon"]) < 1e-4
+    assert _rel(chg2.grad.cpu().numpy(), ref2["charge"]) < 1e-4
