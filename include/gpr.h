@@ -362,6 +362,31 @@ int64_t gpr_advance_steps(const gpr_system *sys);
 gpr_status gpr_batch_advance(gpr_system *const *systems, int32_t nsys, int64_t nsteps,
                              int64_t *const *first_exit_check);
 
+/* The Gen.ParRep calls of several systems with their persistent steps in shared launches.
+ * ops[k] names the call to run on systems[k] (GPR_OP_DECORRELATE: gpr_decorrelate with t_corr and
+ * max_steps; GPR_OP_DEPHASE: gpr_dephase with max_steps; GPR_OP_PARALLEL_STEP: gpr_parallel_step
+ * with max_steps checks) and receives its status (GPR_OK with the result in event, dephase or
+ * exit, GPR_BUDGET, or the error) and result.  Every launch advances each system that is still
+ * running up to the next exit check of any of them, the systems at a check then take it, and
+ * a system whose call is done waits for the others.  Per system every step, check, result and
+ * clock reading is bit-identical to the single-system call.  Systems as in gpr_batch_advance
+ * (1 to 8 distinct handles on one stream, each able to use the persistent path).  Returns
+ * GPR_OK when every call finished with GPR_OK or GPR_BUDGET, else the first error (the other
+ * systems' calls stop where they are). */
+#define GPR_OP_DECORRELATE   0
+#define GPR_OP_DEPHASE       1
+#define GPR_OP_PARALLEL_STEP 2
+typedef struct gpr_batch_op {
+    int32_t op;              /* GPR_OP_* */
+    int32_t status;          /* out */
+    int64_t t_corr;          /* GPR_OP_DECORRELATE: residence time (steps) */
+    int64_t max_steps;       /* budget: steps (decorrelate, dephase) or checks (parallel step) */
+    gpr_event event;         /* out: GPR_OP_DECORRELATE */
+    gpr_dephase_out dephase; /* out: GPR_OP_DEPHASE */
+    gpr_exit_out exit;       /* out: GPR_OP_PARALLEL_STEP */
+} gpr_batch_op;
+gpr_status gpr_batch_run(gpr_system *const *systems, int32_t nsys, gpr_batch_op *ops);
+
 /* Timing of the dominant stepping kernel (the persistent kernel on the persistent path,
  * the pair-force kernel on the plain path) with HIP events recorded on the system's
  * stream around each launch.  gpr_profile enables (1) or disables (0) recording and

@@ -56,7 +56,7 @@ struct gpr_system {
     long long dc_resid = 0, dc_steps = 0;
     long long dp_t = 0, nsamp = 0, n_branch = 0;
     long long adv_t = 0;       // steps taken by gpr_advance / gpr_batch_advance: their sampling and check phase
-    long long par_M = 0;
+    long long par_M = 0, par_t = 0;   // parallel step: checks done, steps into the current check period
     // original ParRep dephasing: start configuration, samples, per-replica progress
     float *snap_x = nullptr, *snap_v = nullptr, *samp_x = nullptr, *samp_v = nullptr;
     long long *snap_F = nullptr, *samp_F = nullptr;
@@ -1379,93 +1379,149 @@ extern "C" gpr_status gpr_observe(gpr_system *S, double *obs, int32_t *state)
 }
 
 // ------------------------------------------------------------------ Gen.ParRep steps
-extern "C" gpr_status gpr_decorrelate(gpr_system *S, int64_t t_corr, int64_t max_steps, gpr_event *ev)
+// Each call (transient propagation, convergence step, parallel step; Fig. 1) is a loop of
+// chunks of steps, each ending at or before the call's next exit check, followed by that
+// check.  PhaseRun holds one call in progress, so that the single-system calls and
+// gpr_batch_run (several systems whose chunks share persistent launches) run one logic.
+namespace {
+struct PhaseRun {
+    int op = 0;                          // GPR_OP_*
+    long long t_corr = 0, budget = 0;    // budget: steps (transient, convergence) or checks (parallel)
+    long long taken = 0;                 // steps (or checks) taken in this call
+    bool done = false;
+    gpr_status rc = GPR_OK;              // when done: GPR_OK (result written) or GPR_BUDGET
+    gpr_event ev{};
+    gpr_dephase_out dout{};
+    gpr_exit_out pout{};
+};
+struct Chunk {
+    int nrep;                            // replicas stepped
+    long long k, t0;                     // steps; local step count at the start (sampling phase)
+    bool sample, at_check;               // workers' observables every t_GR; the chunk ends at a check
+};
+} // namespace
+
+static gpr_status phase_begin(gpr_system *S, PhaseRun &p)
 {
-    if (!S || !ev) return fail(S, GPR_EINVAL, "NULL argument");
     gpr_status rc;
-    if (S->phase != PH_DECORR) {
-        int st0 = -1;
-        rc = state_of_ref(S, &st0);
-        if (rc) return rc;
-        S->phase = PH_DECORR;
-        S->dc_omega = st0;
-        S->dc_from = st0;
-        S->dc_resid = 0;
-        S->dc_steps = 0;
-    }
-    long long taken = 0;
-    for (;;) {
-        if (S->dc_omega != -1 && S->dc_resid >= t_corr) {
-            S->omega = S->dc_omega;
-            S->phase = PH_IDLE;
-            ev->kind = GPR_EV_RESIDENT; ev->from_state = S->dc_from; ev->to_state = S->dc_omega; ev->pad = 0;
-            ev->resident_steps = S->dc_resid; ev->steps_taken = S->dc_steps;
-            return GPR_OK;
+    if (p.op == GPR_OP_DECORRELATE) {
+        if (S->phase != PH_DECORR) {
+            int st0 = -1;
+            rc = state_of_ref(S, &st0);
+            if (rc) return rc;
+            S->phase = PH_DECORR;
+            S->dc_omega = st0;
+            S->dc_from = st0;
+            S->dc_resid = 0;
+            S->dc_steps = 0;
         }
-        if (taken >= max_steps) return GPR_BUDGET;
-        rc = run_steps(S, 1, S->tcd, 0, false, true);
-        if (rc) return rc;
-        S->tsim += S->tcd;
-        taken += S->tcd;
-        S->dc_steps += S->tcd;
+    } else if (p.op == GPR_OP_DEPHASE) {
+        if (S->phase != PH_DEPHASE) {
+            if (S->omega == -1) return fail(S, GPR_EPHASE, "reference walker is in no state");
+            rc = broadcast_reference(S);
+            if (rc) return rc;
+            HIPCHK(S, hipMemsetAsync(S->d.acc, 0, sizeof(double) * S->R * MAX_OBS * 2, S->stream));
+            if (S->d.need_energy) {
+                rc = launch_forces(S, 0, 1, -1, 1, 0, 1);
+                if (rc) return rc;
+            }
+            hipLaunchKernelGGL(k_obs, dim3(1), dim3(256), S->lds_stage, S->stream, S->d_dev, 0, 1, nullptr, 0);
+            LAUNCHCHK(S);
+            S->nsamp = 0;
+            S->dp_t = 0;
+            S->n_branch = 0;
+            S->phase = PH_DEPHASE;
+        }
+    } else if (p.op == GPR_OP_PARALLEL_STEP) {
+        if (S->phase == PH_CONVERGED) { S->phase = PH_PARALLEL; S->par_M = 0; S->par_t = 0; }
+        else if (S->phase != PH_PARALLEL) return fail(S, GPR_EPHASE, "parallel step needs a converged dephasing");
+    } else {
+        return fail(S, GPR_EINVAL, "unknown Gen.ParRep step");
+    }
+    return GPR_OK;
+}
+
+// decisions taken before any further step: residence reached, or the budget spent
+static void phase_ready(gpr_system *S, PhaseRun &p)
+{
+    if (p.done) return;
+    if (p.op == GPR_OP_DECORRELATE && S->dc_omega != -1 && S->dc_resid >= p.t_corr) {
+        S->omega = S->dc_omega;
+        S->phase = PH_IDLE;
+        p.ev.kind = GPR_EV_RESIDENT; p.ev.from_state = S->dc_from; p.ev.to_state = S->dc_omega; p.ev.pad = 0;
+        p.ev.resident_steps = S->dc_resid; p.ev.steps_taken = S->dc_steps;
+        p.done = true; p.rc = GPR_OK;
+        return;
+    }
+    if (p.taken >= p.budget) { p.done = true; p.rc = GPR_BUDGET; }
+}
+
+// the next chunk, at most kmax steps
+static Chunk phase_chunk(const gpr_system *S, const PhaseRun &p, long long kmax)
+{
+    Chunk c{};
+    if (p.op == GPR_OP_DECORRELATE) {
+        const long long pos = S->dc_steps % S->tcd;
+        c.nrep = 1; c.k = S->tcd - pos; c.t0 = 0; c.sample = false;
+        c.k = std::min(c.k, kmax);
+        c.at_check = pos + c.k == S->tcd;
+    } else if (p.op == GPR_OP_DEPHASE) {
+        const long long pos = S->dp_t % S->tcd;
+        c.nrep = S->R; c.t0 = S->dp_t; c.sample = true;
+        c.k = std::min(std::min<long long>(S->tcd - pos, p.budget - p.taken), kmax);
+        c.at_check = pos + c.k == S->tcd;
+    } else {
+        c.nrep = S->R; c.t0 = 0; c.sample = false;
+        c.k = std::min<long long>(S->tcp - S->par_t, kmax);
+        c.at_check = S->par_t + c.k == S->tcp;
+    }
+    return c;
+}
+
+// bookkeeping after a chunk of c.k steps (the steps themselves already taken), then the
+// exit check and the decision it leads to when the chunk ends at a check
+static gpr_status phase_advance(gpr_system *S, PhaseRun &p, const Chunk &c)
+{
+    gpr_status rc;
+    if (p.op == GPR_OP_DECORRELATE) {
+        S->tsim += c.k;
+        p.taken += c.k;
+        S->dc_steps += c.k;
+        if (!c.at_check) return GPR_OK;
         rc = check(S, CHK_STATE, 1, 0);
         if (rc) return rc;
         const int st = S->st_host->to_state;
         if (st == S->dc_omega) {
             S->dc_resid += S->tcd;
         } else if (S->dc_omega == -1) {
-            S->dc_omega = st;
+            S->dc_omega = st;              // entered a state: the reaching time ends here
             S->dc_resid = 0;
         } else {
-            ev->kind = GPR_EV_EXITED; ev->from_state = S->dc_omega; ev->to_state = st; ev->pad = 0;
-            ev->resident_steps = S->dc_resid + S->tcd; ev->steps_taken = S->dc_steps;
+            p.ev.kind = GPR_EV_EXITED; p.ev.from_state = S->dc_omega; p.ev.to_state = st; p.ev.pad = 0;
+            p.ev.resident_steps = S->dc_resid + S->tcd; p.ev.steps_taken = S->dc_steps;
             S->omega = st;
             S->phase = PH_IDLE;
-            return GPR_OK;
+            p.done = true; p.rc = GPR_OK;
         }
+        return GPR_OK;
     }
-}
-
-extern "C" gpr_status gpr_dephase(gpr_system *S, int64_t max_steps, gpr_dephase_out *o)
-{
-    if (!S || !o) return fail(S, GPR_EINVAL, "NULL argument");
-    gpr_status rc;
-    if (S->phase != PH_DEPHASE) {
-        if (S->omega == -1) return fail(S, GPR_EPHASE, "reference walker is in no state");
-        rc = broadcast_reference(S);
-        if (rc) return rc;
-        HIPCHK(S, hipMemsetAsync(S->d.acc, 0, sizeof(double) * S->R * MAX_OBS * 2, S->stream));
-        if (S->d.need_energy) {
-            rc = launch_forces(S, 0, 1, -1, 1, 0, 1);
-            if (rc) return rc;
-        }
-        hipLaunchKernelGGL(k_obs, dim3(1), dim3(256), S->lds_stage, S->stream, S->d_dev, 0, 1, nullptr, 0);
-        LAUNCHCHK(S);
-        S->nsamp = 0;
-        S->dp_t = 0;
-        S->n_branch = 0;
-        S->phase = PH_DEPHASE;
-    }
-    long long taken = 0;
-    while (taken < max_steps) {
-        const long long k = std::min<long long>(S->tcd - S->dp_t % S->tcd, max_steps - taken);
-        const bool at_check = (S->dp_t + k) % S->tcd == 0;
-        rc = run_steps(S, S->R, k, S->dp_t, true, at_check);
-        if (rc) return rc;
-        S->nsamp += count_samples(S->dp_t, S->dp_t + k, S->t_gr);
-        S->dp_t += k;
-        taken += k;
-        if (!at_check) break;
+    if (p.op == GPR_OP_DEPHASE) {
+        S->nsamp += count_samples(S->dp_t, S->dp_t + c.k, S->t_gr);
+        S->dp_t += c.k;
+        p.taken += c.k;
+        if (!c.at_check) return GPR_OK;
         rc = check(S, CHK_DEPHASE, S->R, 0);
         if (rc) return rc;
         const Status &st = *S->st_host;
+        gpr_dephase_out &o = p.dout;
         if (st.ref_exited) {
             S->tsim += S->dp_t;
-            o->outcome = GPR_DEPHASE_REF_EXITED; o->to_state = st.to_state; o->t_steps = S->dp_t;
-            o->n_branch = S->n_branch; o->n_samples = S->nsamp;
-            for (int j = 0; j < GPR_MAX_OBS; ++j) o->rhat[j] = j < S->nobs ? st.rhat[j] : 0.0;
+            o.outcome = GPR_DEPHASE_REF_EXITED; o.to_state = st.to_state; o.t_steps = S->dp_t;
+            o.n_branch = S->n_branch; o.n_samples = S->nsamp;
+            for (int j = 0; j < GPR_MAX_OBS; ++j) o.rhat[j] = j < S->nobs ? st.rhat[j] : 0.0;
             S->omega = st.to_state;
             S->phase = PH_IDLE;
+            p.done = true; p.rc = GPR_OK;
             return GPR_OK;
         }
         if (st.n_surv == 0 && S->R > 1) {
@@ -1478,14 +1534,74 @@ extern "C" gpr_status gpr_dephase(gpr_system *S, int64_t max_steps, gpr_dephase_
         for (int j = 0; j < S->nobs && conv; ++j) conv = st.rhat[j] < 1.0 + S->tol;
         if (conv) {
             S->tsim += S->dp_t;
-            o->outcome = GPR_DEPHASE_CONVERGED; o->to_state = S->omega; o->t_steps = S->dp_t;
-            o->n_branch = S->n_branch; o->n_samples = S->nsamp;
-            for (int j = 0; j < GPR_MAX_OBS; ++j) o->rhat[j] = j < S->nobs ? st.rhat[j] : 0.0;
+            o.outcome = GPR_DEPHASE_CONVERGED; o.to_state = S->omega; o.t_steps = S->dp_t;
+            o.n_branch = S->n_branch; o.n_samples = S->nsamp;
+            for (int j = 0; j < GPR_MAX_OBS; ++j) o.rhat[j] = j < S->nobs ? st.rhat[j] : 0.0;
             S->phase = PH_CONVERGED;
-            return GPR_OK;
+            p.done = true; p.rc = GPR_OK;
         }
+        return GPR_OK;
     }
-    return GPR_BUDGET;
+    // parallel step
+    S->par_t += c.k;
+    if (!c.at_check) return GPR_OK;
+    S->par_t = 0;
+    S->par_M += 1;
+    p.taken += 1;
+    rc = check(S, CHK_PARALLEL, S->R, S->par_M);
+    if (rc) return rc;
+    const int k = S->st_host->k;
+    if (k == 0) return GPR_OK;
+    // M, k and tau of Eq. 5, voted on the device
+    const long long tau = S->st_host->tau;
+    S->tsim += tau;
+    if (k != 1) {
+        rc = copy_replica(S, 0, k - 1);
+        if (rc) return rc;
+    }
+    gpr_exit_out &o = p.pout;
+    o.M = S->st_host->M; o.k = k; o.to_state = S->st_host->to_state; o.tau_steps = tau; o.tau = (double)tau * S->dt;
+    S->omega = S->st_host->to_state;
+    S->phase = PH_IDLE;
+    HIPCHK(S, hipStreamSynchronize(S->stream));
+    p.done = true; p.rc = GPR_OK;
+    return GPR_OK;
+}
+
+static gpr_status run_phase(gpr_system *S, PhaseRun &p)
+{
+    gpr_status rc = phase_begin(S, p);
+    if (rc) return rc;
+    for (;;) {
+        phase_ready(S, p);
+        if (p.done) return p.rc;
+        const Chunk c = phase_chunk(S, p, 1LL << 62);
+        rc = run_steps(S, c.nrep, c.k, c.t0, c.sample, c.at_check);
+        if (rc) return rc;
+        rc = phase_advance(S, p, c);
+        if (rc) return rc;
+        if (p.done) return p.rc;
+    }
+}
+
+extern "C" gpr_status gpr_decorrelate(gpr_system *S, int64_t t_corr, int64_t max_steps, gpr_event *ev)
+{
+    if (!S || !ev) return fail(S, GPR_EINVAL, "NULL argument");
+    PhaseRun p;
+    p.op = GPR_OP_DECORRELATE; p.t_corr = t_corr; p.budget = max_steps;
+    const gpr_status rc = run_phase(S, p);
+    if (rc == GPR_OK) *ev = p.ev;
+    return rc;
+}
+
+extern "C" gpr_status gpr_dephase(gpr_system *S, int64_t max_steps, gpr_dephase_out *o)
+{
+    if (!S || !o) return fail(S, GPR_EINVAL, "NULL argument");
+    PhaseRun p;
+    p.op = GPR_OP_DEPHASE; p.budget = max_steps;
+    const gpr_status rc = run_phase(S, p);
+    if (rc == GPR_OK) *o = p.dout;
+    return rc;
 }
 
 // copies the (x, v, F) of one replica between the system and a replica-sized buffer set
@@ -1584,32 +1700,11 @@ extern "C" gpr_status gpr_dephase_fixed(gpr_system *S, int64_t t_phase, int64_t 
 extern "C" gpr_status gpr_parallel_step(gpr_system *S, int64_t max_checks, gpr_exit_out *o)
 {
     if (!S || !o) return fail(S, GPR_EINVAL, "NULL argument");
-    if (S->phase == PH_CONVERGED) { S->phase = PH_PARALLEL; S->par_M = 0; }
-    else if (S->phase != PH_PARALLEL) return fail(S, GPR_EPHASE, "parallel step needs a converged dephasing");
-    long long checks = 0;
-    while (checks < max_checks) {
-        gpr_status rc = run_steps(S, S->R, S->tcp, 0, false, true);
-        if (rc) return rc;
-        S->par_M += 1;
-        checks += 1;
-        rc = check(S, CHK_PARALLEL, S->R, S->par_M);
-        if (rc) return rc;
-        const int k = S->st_host->k;
-        if (k == 0) continue;
-        // M, k and tau of Eq. 5, voted on the device
-        const long long tau = S->st_host->tau;
-        S->tsim += tau;
-        if (k != 1) {
-            rc = copy_replica(S, 0, k - 1);
-            if (rc) return rc;
-        }
-        o->M = S->st_host->M; o->k = k; o->to_state = S->st_host->to_state; o->tau_steps = tau; o->tau = (double)tau * S->dt;
-        S->omega = S->st_host->to_state;
-        S->phase = PH_IDLE;
-        HIPCHK(S, hipStreamSynchronize(S->stream));
-        return GPR_OK;
-    }
-    return GPR_BUDGET;
+    PhaseRun p;
+    p.op = GPR_OP_PARALLEL_STEP; p.budget = max_checks;
+    const gpr_status rc = run_phase(S, p);
+    if (rc == GPR_OK) *o = p.pout;
+    return rc;
 }
 
 extern "C" gpr_status gpr_advance(gpr_system *S, int64_t nsteps, int64_t *first_exit_check)
@@ -1648,14 +1743,10 @@ extern "C" gpr_status gpr_advance(gpr_system *S, int64_t nsteps, int64_t *first_
 }
 
 // ------------------------------------------------------------------ several systems in one launch
-// gpr_advance of every system, with the persistent steps of all systems in shared launches:
-// each launch runs up to the next exit check of any of them, then the systems at a check run
-// it.  Workgroups are shared out so as to even out the systems' estimated times per step.
-extern "C" gpr_status gpr_batch_advance(gpr_system *const *systems, int32_t nsys, int64_t nsteps,
-                                        int64_t *const *first_exit_check)
+// validation shared by the batch calls
+static gpr_status batch_check(gpr_system *const *systems, int32_t nsys)
 {
     if (!systems || nsys < 1 || nsys > MAX_BATCH) return fail(nullptr, GPR_EINVAL, "1 to 8 systems");
-    if (nsteps < 0) return fail(systems[0], GPR_EINVAL, "nsteps < 0");
     for (int k = 0; k < nsys; ++k) {
         gpr_system *S = systems[k];
         if (!S) return fail(nullptr, GPR_EINVAL, "NULL system");
@@ -1664,40 +1755,59 @@ extern "C" gpr_status gpr_batch_advance(gpr_system *const *systems, int32_t nsys
         if (!S->persist_ok) return fail(S, GPR_EINVAL, "system too large for the persistent path");
         if (S->stream != systems[0]->stream) return fail(S, GPR_EINVAL, "all systems must use one stream");
     }
-    gpr_system *S0 = systems[0];
-    hipStream_t stream = S0->stream;
+    return GPR_OK;
+}
+
+// block size and LDS of a shared launch (the largest of the systems') and the workgroups the
+// device holds at once with them; w[k]: work estimate of one step of all of system k's replicas
+struct BatchShape {
     int bt = 64;
     size_t lds = 0;
-    std::vector<double> w(nsys);
+    int capacity = 0;
+    std::vector<double> w;
+};
+
+static gpr_status batch_shape(gpr_system *const *systems, int32_t nsys, BatchShape &sh)
+{
+    sh.w.assign(nsys, 0.0);
     for (int k = 0; k < nsys; ++k) {
         gpr_system *S = systems[k];
-        bt = std::max(bt, S->bt_persist);
-        lds = std::max(lds, persist_lds(S->n, S->np, S->split));
+        sh.bt = std::max(sh.bt, S->bt_persist);
+        sh.lds = std::max(sh.lds, persist_lds(S->n, S->np, S->split));
         double per = 0.0;
         for (double x : S->work) per += x;
-        w[k] = per * S->R;
+        sh.w[k] = per;
     }
     int dev = 0, cus = 0, per_cu = 0;
-    HIPCHK(S0, hipGetDevice(&dev));
-    HIPCHK(S0, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    HIPCHK(S0, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_persist_batch, bt, lds));
-    const int capacity = per_cu * cus;
-    // sets per system: one each to begin with; then, one set at a time, more for the system
-    // whose replicas would take longest, estimated as (replicas per set) x (time of one
-    // replica-step on one workgroup) / G, that time modelled as 5 us of fixed latency plus
-    // 2.8e-4 us per unit of the per-atom work estimate (both from measured step times).
-    std::vector<int> sets(nsys, 1);
+    HIPCHK(systems[0], hipGetDevice(&dev));
+    HIPCHK(systems[0], hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHK(systems[0], hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_persist_batch, sh.bt, sh.lds));
+    sh.capacity = per_cu * cus;
+    return GPR_OK;
+}
+
+// Items of a shared launch for the systems with nrep[k] > 0 replicas stepped: sets per system
+// one each to begin with; then, one set at a time, more for the system whose replicas would
+// take longest, estimated as (replicas per set) x (time of one replica-step on one workgroup)
+// / G, that time modelled as 5 us of fixed latency plus 2.8e-4 us per unit of the per-atom
+// work estimate (both from measured step times).  slot[k]: the item of system k (-1: none).
+static gpr_status batch_layout(gpr_system *const *systems, int32_t nsys, const std::vector<int> &nrep,
+                               const BatchShape &sh, PersistBatch &pb, std::vector<int> &slot, int &nblocks)
+{
+    gpr_system *S0 = systems[0];
+    std::vector<int> sets(nsys, 0);
     int used = 0;
-    for (int k = 0; k < nsys; ++k) used += systems[k]->groups;
-    if (used > capacity) return fail(S0, GPR_EINVAL, "the systems' workgroups do not fit on the device at once");
+    for (int k = 0; k < nsys; ++k)
+        if (nrep[k] > 0) { sets[k] = 1; used += systems[k]->groups; }
+    if (used > sh.capacity) return fail(S0, GPR_EINVAL, "the systems' workgroups do not fit on the device at once");
     auto est = [&](int k, int ns) {
-        const double t1 = 5.0 + 2.8e-4 * w[k] / systems[k]->R;
-        return (double)((systems[k]->R + ns - 1) / ns) * t1 / systems[k]->groups;
+        const double t1 = 5.0 + 2.8e-4 * sh.w[k];
+        return (double)((nrep[k] + ns - 1) / ns) * t1 / systems[k]->groups;
     };
     for (;;) {
         int pick = -1;
         for (int k = 0; k < nsys; ++k) {
-            if (sets[k] >= systems[k]->R || used + systems[k]->groups > capacity) continue;
+            if (nrep[k] <= 0 || sets[k] >= nrep[k] || used + systems[k]->groups > sh.capacity) continue;
             if (pick < 0 || est(k, sets[k]) > est(pick, sets[pick])) pick = k;
         }
         if (pick < 0) break;
@@ -1705,26 +1815,50 @@ extern "C" gpr_status gpr_batch_advance(gpr_system *const *systems, int32_t nsys
         used += systems[pick]->groups;
     }
     std::vector<PersistItem> items(nsys);
-    std::vector<int> nb(nsys);
+    std::vector<int> nb(nsys, 0);
     for (int k = 0; k < nsys; ++k) {
+        if (nrep[k] <= 0) continue;
         bool coop = false;
-        gpr_status rc = persist_item(systems[k], systems[k]->R, bt, lds, sets[k] * systems[k]->groups, items[k], nb[k], coop);
+        gpr_status rc = persist_item(systems[k], nrep[k], sh.bt, sh.lds, sets[k] * systems[k]->groups, items[k], nb[k], coop);
         if (rc) return rc;
     }
-    std::vector<int> slot(nsys);            // slot[k]: position of system k's item in the launch
-    PersistBatch pb{};
-    pb.nitems = nsys;
+    slot.assign(nsys, -1);
+    pb = PersistBatch{};
     int boff = 0, j = 0;
     for (int pass = 1; pass >= 0; --pass)
         for (int k = 0; k < nsys; ++k) {
-            if (items[k].xcd != pass) continue;
+            if (nrep[k] <= 0 || items[k].xcd != pass) continue;
             items[k].boff = boff;
             boff += nb[k];
             slot[k] = j;
             pb.it[j++] = items[k];
         }
-    if (boff > capacity) return fail(S0, GPR_EINVAL, "the systems' workgroups do not fit on the device at once");
-    const int nblocks = boff;
+    pb.nitems = j;
+    if (boff > sh.capacity) return fail(S0, GPR_EINVAL, "the systems' workgroups do not fit on the device at once");
+    nblocks = boff;
+    return GPR_OK;
+}
+
+// gpr_advance of every system, with the persistent steps of all systems in shared launches:
+// each launch runs up to the next exit check of any of them, then the systems at a check run
+// it.  Workgroups are shared out so as to even out the systems' estimated times per step.
+extern "C" gpr_status gpr_batch_advance(gpr_system *const *systems, int32_t nsys, int64_t nsteps,
+                                        int64_t *const *first_exit_check)
+{
+    gpr_status rc = batch_check(systems, nsys);
+    if (rc) return rc;
+    if (nsteps < 0) return fail(systems[0], GPR_EINVAL, "nsteps < 0");
+    gpr_system *S0 = systems[0];
+    hipStream_t stream = S0->stream;
+    BatchShape sh;
+    rc = batch_shape(systems, nsys, sh);
+    if (rc) return rc;
+    std::vector<int> nrep(nsys), slot;
+    for (int k = 0; k < nsys; ++k) nrep[k] = systems[k]->R;
+    PersistBatch pb{};
+    int nblocks = 0;
+    rc = batch_layout(systems, nsys, nrep, sh, pb, slot, nblocks);
+    if (rc) return rc;
     std::vector<long long> t(nsys, 0);
     for (int k = 0; k < nsys; ++k) t[k] = systems[k]->adv_t;
     for (int k = 0; k < nsys; ++k)
@@ -1744,7 +1878,7 @@ extern "C" gpr_status gpr_batch_advance(gpr_system *const *systems, int32_t nsys
             it.state_end = (t[k] + kstep) % S->tcd == 0 ? 1 : 0;
             if (S->groups > 1) HIPCHK(S, hipMemsetAsync(S->d.sync, 0, sizeof(int) * 64 * S->R, stream));
         }
-        gpr_status rc = launch_persist(S0, pb, nblocks, bt, lds, true, stream);
+        rc = launch_persist(S0, pb, nblocks, sh.bt, sh.lds, true, stream);
         if (rc) return rc;
         for (int k = 0; k < nsys; ++k) {
             gpr_system *S = systems[k];
@@ -1772,6 +1906,84 @@ extern "C" gpr_status gpr_batch_advance(gpr_system *const *systems, int32_t nsys
         if (first_exit_check && first_exit_check[k])
             for (int r = 0; r < S->R; ++r) first_exit_check[k][r] = f[r];
     }
+    return GPR_OK;
+}
+
+// The Gen.ParRep calls of several systems (Fig. 1 steps), their chunks of steps in shared
+// launches: each launch takes every running system up to the nearest exit check among them.
+extern "C" gpr_status gpr_batch_run(gpr_system *const *systems, int32_t nsys, gpr_batch_op *ops)
+{
+    gpr_status rc = batch_check(systems, nsys);
+    if (rc) return rc;
+    if (!ops) return fail(systems[0], GPR_EINVAL, "NULL ops");
+    gpr_system *S0 = systems[0];
+    hipStream_t stream = S0->stream;
+    BatchShape sh;
+    rc = batch_shape(systems, nsys, sh);
+    if (rc) return rc;
+    std::vector<PhaseRun> p(nsys);
+    for (int k = 0; k < nsys; ++k) {
+        p[k].op = ops[k].op;
+        p[k].t_corr = ops[k].t_corr;
+        p[k].budget = ops[k].max_steps;
+        ops[k].status = GPR_BUDGET;
+    }
+    auto finish = [&](int k) {
+        ops[k].status = p[k].rc;
+        if (p[k].rc == GPR_OK) {
+            if (p[k].op == GPR_OP_DECORRELATE) ops[k].event = p[k].ev;
+            else if (p[k].op == GPR_OP_DEPHASE) ops[k].dephase = p[k].dout;
+            else ops[k].exit = p[k].pout;
+        }
+    };
+    for (int k = 0; k < nsys; ++k) {
+        rc = phase_begin(systems[k], p[k]);
+        if (rc) { ops[k].status = rc; return rc; }
+    }
+    std::vector<int> nrep(nsys), slot, last_nrep;
+    std::vector<Chunk> c(nsys);
+    PersistBatch pb{};
+    int nblocks = 0;
+    for (;;) {
+        long long kstep = 1LL << 20;
+        int active = 0;
+        for (int k = 0; k < nsys; ++k) {
+            phase_ready(systems[k], p[k]);
+            nrep[k] = 0;
+            if (p[k].done) continue;
+            c[k] = phase_chunk(systems[k], p[k], 1LL << 62);
+            kstep = std::min(kstep, c[k].k);
+            nrep[k] = c[k].nrep;
+            ++active;
+        }
+        if (active == 0) break;
+        if (nrep != last_nrep) {                          // the running systems or their replica counts changed
+            rc = batch_layout(systems, nsys, nrep, sh, pb, slot, nblocks);
+            if (rc) return rc;
+            last_nrep = nrep;
+        }
+        for (int k = 0; k < nsys; ++k) {
+            if (nrep[k] == 0) continue;
+            gpr_system *S = systems[k];
+            c[k] = phase_chunk(S, p[k], kstep);
+            PersistItem &it = pb.it[slot[k]];
+            it.s0 = S->s;
+            it.nsteps = (int)kstep;
+            it.t0 = (int)(c[k].t0 % S->t_gr);
+            it.sample = c[k].sample ? 1 : 0;
+            it.state_end = c[k].at_check ? 1 : 0;
+            if (S->groups > 1) HIPCHK(S, hipMemsetAsync(S->d.sync, 0, sizeof(int) * 64 * S->R, stream));
+        }
+        rc = launch_persist(S0, pb, nblocks, sh.bt, sh.lds, true, stream);
+        if (rc) return rc;
+        for (int k = 0; k < nsys; ++k) {
+            if (nrep[k] == 0) continue;
+            systems[k]->s += kstep;
+            rc = phase_advance(systems[k], p[k], c[k]);
+            if (rc) { ops[k].status = rc; return rc; }
+        }
+    }
+    for (int k = 0; k < nsys; ++k) finish(k);
     return GPR_OK;
 }
 

@@ -78,6 +78,13 @@ class _Exit(C.Structure):
 
 
 # every entry point of include/gpr.h with its ctypes signature
+class _BatchOp(C.Structure):
+    _fields_ = [("op", C.c_int32), ("status", C.c_int32), ("t_corr", C.c_int64), ("max_steps", C.c_int64),
+                ("event", _Event), ("dephase", _Dephase), ("exit", _Exit)]
+
+
+OP_DECORRELATE, OP_DEPHASE, OP_PARALLEL_STEP = 0, 1, 2
+
 _VP = C.c_void_p
 _P64 = C.POINTER(C.c_int64)
 SIGNATURES = {
@@ -113,6 +120,7 @@ SIGNATURES = {
     "gpr_autotune": (C.c_int32, [_VP, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "gpr_set_graph": (C.c_int32, [_VP, C.c_int32]),
     "gpr_batch_advance": (C.c_int32, [C.POINTER(_VP), C.c_int32, C.c_int64, C.POINTER(_P64)]),
+    "gpr_batch_run": (C.c_int32, [C.POINTER(_VP), C.c_int32, C.POINTER(_BatchOp)]),
     "gpr_set_params": (C.c_int32, [_VP, _PD, _PD, _PD, _PD]),
     "gpr_energy_forces_dev": (C.c_int32, [_VP, C.c_void_p, C.c_void_p, C.c_void_p]),
     "gpr_energy_backward_dev": (C.c_int32, [_VP, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -395,6 +403,43 @@ def batch_advance(systems, nsteps):
     ptrs = (_P64 * len(systems))(*[f.ctypes.data_as(_P64) for f in fec])
     _check(lib().gpr_batch_advance(hs, len(systems), int(nsteps), ptrs), systems[0]._h)
     return fec
+
+
+def _event_dict(ev):
+    return dict(kind=ev.kind, from_state=ev.from_state, to_state=ev.to_state,
+                resident_steps=ev.resident_steps, steps_taken=ev.steps_taken)
+
+
+def _dephase_dict(o, nobs):
+    return dict(outcome=o.outcome, to_state=o.to_state, t_steps=o.t_steps, n_branch=o.n_branch,
+                n_samples=o.n_samples, rhat=list(o.rhat)[:nobs])
+
+
+def _exit_dict(o):
+    return dict(M=o.M, k=o.k, to_state=o.to_state, tau_steps=o.tau_steps, tau=o.tau)
+
+
+def batch_run(systems, ops):
+    """Gen.ParRep calls of several systems with their steps in shared persistent launches.
+    ops[k]: dict(op=OP_DECORRELATE | OP_DEPHASE | OP_PARALLEL_STEP, t_corr=..., max_steps=...);
+    returns [(status, result dict as the single-system call returns it)]."""
+    hs = (_VP * len(systems))(*[x._h for x in systems])
+    arr = (_BatchOp * len(systems))()
+    for a, o in zip(arr, ops):
+        a.op = int(o["op"])
+        a.t_corr = int(o.get("t_corr", 0))
+        a.max_steps = int(o.get("max_steps", 1 << 62))
+    _check(lib().gpr_batch_run(hs, len(systems), arr), systems[0]._h)
+    out = []
+    for a, x in zip(arr, systems):
+        if a.op == OP_DECORRELATE:
+            res = _event_dict(a.event)
+        elif a.op == OP_DEPHASE:
+            res = _dephase_dict(a.dephase, x.nobs)
+        else:
+            res = _exit_dict(a.exit)
+        out.append((a.status, res))
+    return out
 
 
 # ------------------------------------------------------------------ building blocks

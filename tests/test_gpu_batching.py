@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import gpr_synth as G
+import oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -95,3 +96,89 @@ def test_batch_advance_refuses_bad_input():
     # eight is the most a shared launch takes
     f = gpr.batch_advance(many[:8], 20)
     assert len(f) == 8 and all(x.global_step() == 20 for x in many[:8])
+
+
+def _batch_gen_parrep(gpr, systems, n_exits, t_corrs):
+    """The loop of Fig. 1 on several systems at once through gpr_batch_run: each system's next
+    call follows its own previous result, as in helpers.gen_parrep_exits; systems with enough
+    events drop out."""
+    logs = [[] for _ in systems]
+    last = [s.simulated_steps() for s in systems]
+    omega = [s.current_state() for s in systems]
+    nxt = [gpr.OP_DECORRELATE] * len(systems)
+    rounds = 0
+    while any(len(l) < n_exits for l in logs):
+        rounds += 1
+        assert rounds < 500, logs
+        print("round", rounds, [len(l) for l in logs], nxt, flush=True)
+        idx = [k for k in range(len(systems)) if len(logs[k]) < n_exits]
+        ops = [dict(op=nxt[k], t_corr=t_corrs[k]) for k in idx]
+        res = gpr.batch_run([systems[k] for k in idx], ops)
+        for k, (st, r) in zip(idx, res):
+            assert st == 0
+            s = systems[k]
+            if nxt[k] == gpr.OP_DECORRELATE:
+                if r["kind"] == 1:
+                    now = s.simulated_steps()
+                    logs[k].append((now - last[k], r["from_state"], r["to_state"], "transient", 0))
+                    last[k], omega[k] = now, r["to_state"]
+                else:
+                    nxt[k] = gpr.OP_DEPHASE
+            elif nxt[k] == gpr.OP_DEPHASE:
+                if r["outcome"] == 1:
+                    now = s.simulated_steps()
+                    logs[k].append((now - last[k], omega[k], r["to_state"], "dephase", 0))
+                    last[k], omega[k] = now, r["to_state"]
+                    nxt[k] = gpr.OP_DECORRELATE
+                else:
+                    nxt[k] = gpr.OP_PARALLEL_STEP
+            else:
+                now = s.simulated_steps()
+                logs[k].append((now - last[k], omega[k], r["to_state"], "parallel", r["tau_steps"]))
+                last[k], omega[k] = now, r["to_state"]
+                nxt[k] = gpr.OP_DECORRELATE
+    return logs
+
+
+def test_batch_gen_parrep_matches_separate_systems():
+    """The Gen.ParRep loop (transient step, convergence step with branching, parallel step) on
+    three systems whose steps share persistent launches (the toy with checks every 10 steps, a
+    22-atom chain and a 300-atom receptor-ligand system, each with its state split near its
+    start so that exits come within a few checks, checked every 250 and 200 steps): every event,
+    its time and the clock equal the same loop run on each system alone, and the final
+    configurations are bit-identical."""
+    from helpers import gen_parrep_exits
+    gpr = _gpr()
+    toy = dict(G.toy2d(n_replicas=16, seed=7), pos=np.array([[-0.3], [0.0], [0.0]]))
+    # convergence at the first check for the chain and the receptor-ligand system (a tolerance
+    # their R-hat always meets), so that their loops reach parallel steps within seconds; the
+    # toy converges on R-hat below 1.05
+    chain = G.chain(seed=3, n_replicas=8, t_check=250, t_check_parallel=250, tol=1e9)
+    psi_b = -np.pi / 2 + 0.08
+    chain["state"] = dict(kind=G.STATE_DIHEDRAL_BOXES, atoms=chain["state"]["atoms"],
+                          boxes=[[-4.0, 4.0, -4.0, psi_b], [-4.0, 4.0, psi_b, 4.0]])
+    # the 300-atom system with its state split at the current value of a ligand dihedral, so
+    # that the walker leaves and comes back within a few checks
+    rl = G.config("rl300", n_replicas=8, t_check=200, tol=1e9)
+    L = rl["n_atoms"] - 32 + 10
+    dih = [L, L + 1, L + 2, L + 3]
+    o = oracle.System(dict(rl, n_replicas=2, obs=[dict(kind=G.OBS_DIHEDRAL, atoms=dih)]))
+    phi0 = o.observables_of(rl["pos"], np.zeros((3, rl["n_atoms"])), 0.0)[0]
+    cut = phi0 + 0.05
+    rl["state"] = dict(kind=G.STATE_DIHEDRAL_BOXES, atoms=dih + dih,
+                       boxes=[[-4.0, cut, -4.0, 4.0], [cut, 4.0, -4.0, 4.0]])
+    assert abs(phi0) < np.pi - 0.1
+    specs, t_corrs, n = [toy, chain, rl], [100, 500, 400], 3
+    batch = [gpr.System(s, path=gpr.PATH_PERSISTENT) for s in specs]
+    print("batched Gen.ParRep", flush=True)
+    logs = _batch_gen_parrep(gpr, batch, n, t_corrs)
+    for k, spec in enumerate(specs):
+        solo = gpr.System(spec, path=gpr.PATH_PERSISTENT)
+        print("solo Gen.ParRep", k, flush=True)
+        ref = gen_parrep_exits(solo, n, t_corrs[k])
+        assert logs[k] == ref, (k, logs[k], ref)
+        assert batch[k].simulated_steps() == solo.simulated_steps()
+        assert batch[k].global_step() == solo.global_step()
+        _same(batch[k], solo, range(spec["n_replicas"]))
+    kinds = {e[3] for l in logs for e in l}
+    assert "parallel" in kinds
