@@ -387,6 +387,18 @@ typedef struct gpr_batch_op {
 } gpr_batch_op;
 gpr_status gpr_batch_run(gpr_system *const *systems, int32_t nsys, gpr_batch_op *ops);
 
+/* Convergence and parallel steps on the persistent path as replays of a captured HIP graph of
+ * `cycles` check cycles (0 = off, the default: one launch and one status read-back per check).
+ * A cycle is the persistent launch of one check period, with the state test at its end, then
+ * the check launch (Fleming-Viot clone-on-kill, R-hat, the exit vote and the decision whether
+ * the call ends there); once a check ends the call, the rest of the replay does nothing.  The
+ * host reads the statuses of a replay once and takes the same decisions as after a check it
+ * runs itself, so results are bit-identical to cycles = 0.  A replay runs only from a check
+ * boundary with room in the call's budget for all its cycles; other steps run as with
+ * cycles = 0.  0 <= cycles <= 4096; EINVAL for a system too large for the persistent path.
+ * Changing the launch shape (gpr_set_launch, gpr_autotune) discards the captured graphs. */
+gpr_status gpr_set_cycles(gpr_system *sys, int32_t cycles);
+
 /* Timing of the dominant stepping kernel (the persistent kernel on the persistent path,
  * the pair-force kernel on the plain path) with HIP events recorded on the system's
  * stream around each launch.  gpr_profile enables (1) or disables (0) recording and

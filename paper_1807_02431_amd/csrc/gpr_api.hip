@@ -66,6 +66,12 @@ struct gpr_system {
     int graph_cycle = 0;
     struct Graph { int nrep, code, phase; hipGraphExec_t exec; };
     std::vector<Graph> graphs;
+    // persistent convergence and parallel steps as replays of captured check cycles (0: off)
+    int cycles = 0;
+    struct CGraph { int op; hipGraphExec_t exec; };
+    std::vector<CGraph> cgraphs;
+    CycRec *cyc_dev = nullptr, *cyc_host = nullptr;
+    Status *stc_dev = nullptr, *stc_host = nullptr;   // [cycles] statuses of a replay
     // scratch
     Status *st_dev = nullptr, *st_host = nullptr;
     double *obs_out = nullptr;
@@ -158,6 +164,8 @@ void sort_terms(const int32_t *atoms, int cnt, int w, int n, std::vector<int> &o
 long long count_samples(long long t_old, long long t_new, int t_gr) { return t_new / t_gr - t_old / t_gr; }
 
 } // namespace
+
+static void drop_cycle_graphs(gpr_system *S);
 
 // event pair around the next timed launch (created on first use, reused afterwards)
 static hipError_t prof_begin(gpr_system *S)
@@ -511,21 +519,28 @@ static gpr_status run_steps(gpr_system *S, int nrep, long long nsteps, long long
     return GPR_OK;
 }
 
+// the error flags a check copied into its status
+static gpr_status status_errors(gpr_system *S, const Status &st)
+{
+    if (st.err[ERR_UNSTABLE]) return fail(S, GPR_EUNSTABLE, "non-finite or overflowing state");
+    if (st.err[ERR_LIST]) return fail(S, GPR_EDEVICE, "pair-list capacity exceeded");
+    if (st.err[ERR_BARRIER]) return fail(S, GPR_EDEVICE, "persistent-kernel barrier timed out");
+    return GPR_OK;
+}
+
 // one launch: bookkeeping by block (0, 0), and with CHK_DEPHASE the clone-on-kill copies by
 // the blocks of each killed worker's row
 static gpr_status check(gpr_system *S, int mode, int nrep, long long check_index)
 {
     const dim3 grid = mode == CHK_DEPHASE ? dim3((3 * S->np + 255) / 256, nrep) : dim3(1, 1);
     hipLaunchKernelGGL(k_check, grid, dim3(256), sizeof(int) * nrep, S->stream, S->d_dev, mode, S->s, S->omega, nrep,
-                       S->nsamp, check_index, (long long)S->tcp, S->st_dev, S->donor, S->surv, S->fec);
+                       S->nsamp, check_index, (long long)S->tcp, S->st_dev, S->donor, S->surv, S->fec,
+                       (CycRec *)nullptr, 0);
     LAUNCHCHK(S);
     HIPCHK(S, hipMemcpyAsync(S->st_host, S->st_dev, sizeof(Status), hipMemcpyDeviceToHost, S->stream));
     HIPCHK(S, hipStreamSynchronize(S->stream));
     HIPCHK(S, prof_collect(S));
-    if (S->st_host->err[ERR_UNSTABLE]) return fail(S, GPR_EUNSTABLE, "non-finite or overflowing state");
-    if (S->st_host->err[ERR_LIST]) return fail(S, GPR_EDEVICE, "pair-list capacity exceeded");
-    if (S->st_host->err[ERR_BARRIER]) return fail(S, GPR_EDEVICE, "persistent-kernel barrier timed out");
-    return GPR_OK;
+    return status_errors(S, *S->st_host);
 }
 
 static gpr_status copy_replica(gpr_system *S, int dst, int src)
@@ -564,6 +579,11 @@ extern "C" void gpr_system_destroy(gpr_system *S)
     if (!S) return;
     if (S->stream) (void)hipStreamSynchronize(S->stream);
     for (auto &g : S->graphs) (void)hipGraphExecDestroy(g.exec);
+    for (auto &g : S->cgraphs) (void)hipGraphExecDestroy(g.exec);
+    if (S->cyc_dev) (void)hipFree(S->cyc_dev);
+    if (S->stc_dev) (void)hipFree(S->stc_dev);
+    if (S->cyc_host) (void)hipHostFree(S->cyc_host);
+    if (S->stc_host) (void)hipHostFree(S->stc_host);
     for (void *p : S->bufs) (void)hipFree(p);
     for (hipEvent_t e : S->ev_a) (void)hipEventDestroy(e);
     for (hipEvent_t e : S->ev_b) (void)hipEventDestroy(e);
@@ -818,6 +838,8 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
     d.key0 = (uint32_t)D->seed;
     d.key1 = (uint32_t)(D->seed >> 32);
     d.t_gr = D->t_gr;
+    d.tol = D->tol;
+    d.t_min = D->t_min;
     // force-field parameters kept on the host, device buffers of the parameter gradient
     S->mass_h.assign(D->mass, D->mass + n);
     if (D->kind == GPR_KIND_MOLECULAR) {
@@ -1042,6 +1064,7 @@ extern "C" gpr_status gpr_set_launch(gpr_system *S, int32_t block_threads, int32
         HIPCHK(S, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_persist, bt, lds));
         if (per_cu < 1) return fail(S, GPR_EINVAL, "a workgroup of this shape does not fit on a compute unit");
     }
+    drop_cycle_graphs(S);                                   // captured with the old shape
     S->bt_persist = bt;
     if (groups_per_replica != 0) {
         S->groups = groups_per_replica;
@@ -1058,6 +1081,7 @@ extern "C" gpr_status gpr_set_launch(gpr_system *S, int32_t block_threads, int32
 // (results do not depend on the shape or on when lists are rebuilt).
 extern "C" gpr_status gpr_autotune(gpr_system *S, int32_t nsteps, int32_t *block_threads, int32_t *groups)
 {
+    if (S) drop_cycle_graphs(S);                            // captured with the old shape
     if (!S) return fail(nullptr, GPR_EINVAL, "NULL system");
     if (nsteps < 1) return fail(S, GPR_EINVAL, "nsteps < 1");
     if (!S->persist_ok) return fail(S, GPR_EINVAL, "system too large for the persistent path");
@@ -1153,6 +1177,25 @@ extern "C" gpr_status gpr_autotune(gpr_system *S, int32_t nsteps, int32_t *block
     S->split = make_split(S->work, S->n, S->np, best_g);
     if (block_threads) *block_threads = best_bt;
     if (groups) *groups = best_g;
+    return GPR_OK;
+}
+
+extern "C" gpr_status gpr_set_cycles(gpr_system *S, int32_t cycles)
+{
+    if (!S) return fail(nullptr, GPR_EINVAL, "NULL system");
+    if (cycles < 0 || cycles > 4096) return fail(S, GPR_EINVAL, "cycles must be in [0, 4096]");
+    if (cycles > 0 && !S->persist_ok) return fail(S, GPR_EINVAL, "system too large for the persistent path");
+    if (cycles == S->cycles) return GPR_OK;
+    drop_cycle_graphs(S);
+    if (S->stc_dev) { (void)hipFree(S->stc_dev); S->stc_dev = nullptr; }
+    if (S->stc_host) { (void)hipHostFree(S->stc_host); S->stc_host = nullptr; }
+    S->cycles = 0;
+    if (cycles == 0) return GPR_OK;
+    if (!S->cyc_dev) HIPCHK(S, hipMalloc((void **)&S->cyc_dev, sizeof(CycRec)));
+    if (!S->cyc_host) HIPCHK(S, hipHostMalloc((void **)&S->cyc_host, sizeof(CycRec), hipHostMallocDefault));
+    HIPCHK(S, hipMalloc((void **)&S->stc_dev, sizeof(Status) * cycles));
+    HIPCHK(S, hipHostMalloc((void **)&S->stc_host, sizeof(Status) * cycles, hipHostMallocDefault));
+    S->cycles = cycles;
     return GPR_OK;
 }
 
@@ -1478,9 +1521,10 @@ static Chunk phase_chunk(const gpr_system *S, const PhaseRun &p, long long kmax)
     return c;
 }
 
-// bookkeeping after a chunk of c.k steps (the steps themselves already taken), then the
-// exit check and the decision it leads to when the chunk ends at a check
-static gpr_status phase_advance(gpr_system *S, PhaseRun &p, const Chunk &c)
+// bookkeeping after a chunk of c.k steps (the steps themselves already taken), then, when
+// the chunk ends at a check, the decision the check's status leads to: the status comes from
+// running the check (st == nullptr) or from a replay of captured check cycles
+static gpr_status phase_advance(gpr_system *S, PhaseRun &p, const Chunk &c, const Status *stc = nullptr)
 {
     gpr_status rc;
     if (p.op == GPR_OP_DECORRELATE) {
@@ -1510,9 +1554,11 @@ static gpr_status phase_advance(gpr_system *S, PhaseRun &p, const Chunk &c)
         S->dp_t += c.k;
         p.taken += c.k;
         if (!c.at_check) return GPR_OK;
-        rc = check(S, CHK_DEPHASE, S->R, 0);
-        if (rc) return rc;
-        const Status &st = *S->st_host;
+        if (!stc) {
+            rc = check(S, CHK_DEPHASE, S->R, 0);
+            if (rc) return rc;
+        }
+        const Status &st = stc ? *stc : *S->st_host;
         gpr_dephase_out &o = p.dout;
         if (st.ref_exited) {
             S->tsim += S->dp_t;
@@ -1548,25 +1594,30 @@ static gpr_status phase_advance(gpr_system *S, PhaseRun &p, const Chunk &c)
     S->par_t = 0;
     S->par_M += 1;
     p.taken += 1;
-    rc = check(S, CHK_PARALLEL, S->R, S->par_M);
-    if (rc) return rc;
-    const int k = S->st_host->k;
+    if (!stc) {
+        rc = check(S, CHK_PARALLEL, S->R, S->par_M);
+        if (rc) return rc;
+    }
+    const Status &st = stc ? *stc : *S->st_host;
+    const int k = st.k;
     if (k == 0) return GPR_OK;
     // M, k and tau of Eq. 5, voted on the device
-    const long long tau = S->st_host->tau;
+    const long long tau = st.tau;
     S->tsim += tau;
     if (k != 1) {
         rc = copy_replica(S, 0, k - 1);
         if (rc) return rc;
     }
     gpr_exit_out &o = p.pout;
-    o.M = S->st_host->M; o.k = k; o.to_state = S->st_host->to_state; o.tau_steps = tau; o.tau = (double)tau * S->dt;
-    S->omega = S->st_host->to_state;
+    o.M = st.M; o.k = k; o.to_state = st.to_state; o.tau_steps = tau; o.tau = (double)tau * S->dt;
+    S->omega = st.to_state;
     S->phase = PH_IDLE;
     HIPCHK(S, hipStreamSynchronize(S->stream));
     p.done = true; p.rc = GPR_OK;
     return GPR_OK;
 }
+
+static gpr_status run_cycles(gpr_system *S, PhaseRun &p, bool &ran);
 
 static gpr_status run_phase(gpr_system *S, PhaseRun &p)
 {
@@ -1575,6 +1626,10 @@ static gpr_status run_phase(gpr_system *S, PhaseRun &p)
     for (;;) {
         phase_ready(S, p);
         if (p.done) return p.rc;
+        bool ran = false;
+        rc = run_cycles(S, p, ran);
+        if (rc) return rc;
+        if (ran) continue;
         const Chunk c = phase_chunk(S, p, 1LL << 62);
         rc = run_steps(S, c.nrep, c.k, c.t0, c.sample, c.at_check);
         if (rc) return rc;
@@ -1582,6 +1637,130 @@ static gpr_status run_phase(gpr_system *S, PhaseRun &p)
         if (rc) return rc;
         if (p.done) return p.rc;
     }
+}
+
+static void drop_cycle_graphs(gpr_system *S)
+{
+    if (S->stream) (void)hipStreamSynchronize(S->stream);
+    for (auto &g : S->cgraphs) (void)hipGraphExecDestroy(g.exec);
+    S->cgraphs.clear();
+}
+
+// The captured run of S->cycles check cycles of the convergence step (op GPR_OP_DEPHASE) or
+// the parallel step on the persistent path, captured on a stream of its own the first time
+// it is needed.  Per cycle: the replicas' barrier counters cleared by a kernel, the persistent
+// launch(es) of one check period with the state test at the end, then the check with its
+// clone-on-kill copies.  Steps, check indices and Omega come from the cycle record, which the
+// host writes before each replay.
+static gpr_status cycle_graph(gpr_system *S, int op, hipGraphExec_t *out)
+{
+    for (auto &g : S->cgraphs)
+        if (g.op == op) { *out = g.exec; return GPR_OK; }
+    const int nrep = S->R;
+    const bool dep = op == GPR_OP_DEPHASE;
+    const int nsteps = dep ? S->tcd : S->tcp;
+    PersistBatch pb{};
+    pb.nitems = 1;
+    int nblocks = 0;
+    bool coop = false;
+    const size_t lds = persist_lds(S->n, S->np, S->split);
+    gpr_status rc = persist_item(S, nrep, S->bt_persist, lds, -1, pb.it[0], nblocks, coop);
+    if (rc) return rc;
+    const int rounds = (nrep + pb.it[0].nsets - 1) / pb.it[0].nsets;
+    const dim3 cgrid = dep ? dim3((3 * S->np + 255) / 256, nrep) : dim3(1, 1);
+    hipStream_t cs = nullptr;
+    HIPCHK(S, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    for (int j = 0; j < S->cycles && e == hipSuccess; ++j) {
+        PersistItem it = pb.it[0];
+        it.s0 = 0; it.t0 = 0; it.nsteps = nsteps; it.sample = dep ? 1 : 0; it.state_end = 1;
+        it.cyc = S->cyc_dev;
+        it.cycle = j;
+        for (int k = 0; k < rounds && e == hipSuccess; ++k) {
+            it.roff = k * it.nsets;
+            if (S->groups > 1) {
+                hipLaunchKernelGGL(k_zero_ints, dim3((64 * nrep + 255) / 256), dim3(256), 0, cs, S->d.sync, 64 * nrep);
+                e = hipGetLastError();
+                if (e != hipSuccess) break;
+            }
+            void *args[] = {(void *)&it};
+            if (coop) {
+                hipLaunchAttribute attr{};
+                attr.id = hipLaunchAttributeCooperative;
+                attr.val.cooperative = 1;
+                hipLaunchConfig_t cfg{};
+                cfg.gridDim = dim3(nblocks);
+                cfg.blockDim = dim3(S->bt_persist);
+                cfg.dynamicSmemBytes = lds;
+                cfg.stream = cs;
+                cfg.attrs = &attr;
+                cfg.numAttrs = 1;
+                e = hipLaunchKernelExC(&cfg, (const void *)k_persist, args);
+            } else {
+                e = hipLaunchKernel((const void *)k_persist, dim3(nblocks), dim3(S->bt_persist), args, lds, cs);
+            }
+        }
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(k_check, cgrid, dim3(256), sizeof(int) * nrep, cs, S->d_dev, dep ? CHK_DEPHASE : CHK_PARALLEL,
+                           0LL, 0, nrep, 0LL, 0LL, (long long)S->tcp, S->stc_dev, S->donor, S->surv, S->fec, S->cyc_dev, j);
+        e = hipGetLastError();
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &g);
+    hipGraphExec_t ex = nullptr;
+    hipError_t e3 = hipSuccess;
+    if (e == hipSuccess && e2 == hipSuccess) e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
+        return fail(S, GPR_EDEVICE, std::string("check-cycle capture: ") +
+                                        hipGetErrorString(e != hipSuccess ? e : e2 != hipSuccess ? e2 : e3));
+    S->cgraphs.push_back({op, ex});
+    *out = ex;
+    return GPR_OK;
+}
+
+// S->cycles check cycles replayed from the captured graph, when the call stands at a check
+// boundary with room in its budget for all of them; then the host takes, cycle by cycle, the
+// decision each status leads to, exactly as after a check it runs itself, and verifies that
+// the call ends at the cycle the device stopped at.
+static gpr_status run_cycles(gpr_system *S, PhaseRun &p, bool &ran)
+{
+    ran = false;
+    const int C = S->cycles;
+    if (C <= 0 || S->path != GPR_PATH_PERSISTENT || (p.op != GPR_OP_DEPHASE && p.op != GPR_OP_PARALLEL_STEP))
+        return GPR_OK;
+    const bool dep = p.op == GPR_OP_DEPHASE;
+    const long long per = dep ? S->tcd : S->tcp;
+    if (dep ? (S->dp_t % S->tcd != 0 || p.budget - p.taken < C * per) : (S->par_t != 0 || p.budget - p.taken < C))
+        return GPR_OK;
+    hipGraphExec_t ex = nullptr;
+    gpr_status rc = cycle_graph(S, p.op, &ex);
+    if (rc) return rc;
+    CycRec &h = *S->cyc_host;
+    h.s_start = S->s; h.t_start = dep ? S->dp_t : 0; h.M_start = S->par_M; h.nsamp = S->nsamp;
+    h.nsteps = (int)per; h.halt_cycle = NO_HALT; h.omega = S->omega; h.pad = 0;
+    HIPCHK(S, hipMemcpyAsync(S->cyc_dev, S->cyc_host, sizeof(CycRec), hipMemcpyHostToDevice, S->stream));
+    HIPCHK(S, hipGraphLaunch(ex, S->stream));
+    HIPCHK(S, hipMemcpyAsync(S->stc_host, S->stc_dev, sizeof(Status) * C, hipMemcpyDeviceToHost, S->stream));
+    HIPCHK(S, hipMemcpyAsync(S->cyc_host, S->cyc_dev, sizeof(CycRec), hipMemcpyDeviceToHost, S->stream));
+    HIPCHK(S, hipStreamSynchronize(S->stream));
+    ran = true;
+    const int halt = S->cyc_host->halt_cycle;
+    const int ncyc = halt == NO_HALT ? C : halt + 1;
+    for (int j = 0; j < ncyc; ++j) {
+        const Status &st = S->stc_host[j];
+        rc = status_errors(S, st);
+        if (rc) return rc;
+        Chunk c{};
+        c.nrep = S->R; c.k = per; c.t0 = dep ? S->dp_t : 0; c.sample = dep; c.at_check = true;
+        S->s += per;
+        rc = phase_advance(S, p, c, &st);
+        if (rc) return rc;
+        if (p.done != (j == halt)) return fail(S, GPR_EDEVICE, "check cycles: device and host disagree on the end of the call");
+        if (p.done) break;
+    }
+    return GPR_OK;
 }
 
 extern "C" gpr_status gpr_decorrelate(gpr_system *S, int64_t t_corr, int64_t max_steps, gpr_event *ev)

@@ -116,6 +116,8 @@ struct Dev {
     int cutoff_on, period;
     uint32_t key0, key1;
     int t_gr;
+    double tol;                            // convergence: R-hat < 1 + tol for every observable
+    long long t_min;                       // convergence: at least t_min steps of dephasing
 };
 
 // Pointers read from the device-resident descriptor are generic; casting them to the global

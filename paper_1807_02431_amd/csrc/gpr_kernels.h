@@ -20,6 +20,18 @@ struct Status {
     double rhat[MAX_OBS];
 };
 
+// Device record of a captured run of check cycles (a persistent launch, then the check):
+// cycle j of a replay steps from s_start + j nsteps (local step t_start + j nsteps) and takes
+// check index M_start + j + 1; the check that ends the call records its cycle in halt_cycle,
+// and every later kernel of the replay returns at once.  nsamp: observable samples so far.
+struct CycRec {
+    long long s_start, t_start, M_start, nsamp;
+    int nsteps, halt_cycle;
+    int omega;          // the state the checks compare with
+    int pad;
+};
+constexpr int NO_HALT = 0x7FFFFFFF;
+
 // atom ranges of the workgroups of one replica on the persistent path
 struct Split {
     int G;          // workgroups per replica (1, 2, 4 or 8)
@@ -47,6 +59,8 @@ struct PersistItem {
     int roff;           // k_persist: set k takes replica roff + k
     int boff;           // first workgroup of the item in the grid
     int xcd;            // map a set's workgroups to one XCD (nsets and boff multiples of 8)
+    const CycRec *cyc;  // non-null: cycle `cycle` of a captured run (s0 and t0 from the record)
+    int cycle;
 };
 constexpr int MAX_BATCH = 8;
 struct PersistBatch {
@@ -62,7 +76,9 @@ __global__ void k_grad_finish(const Dev *__restrict__ Sp, double *d_eps, double 
 __global__ void k_unfix_out(const Dev *__restrict__ Sp, double *energy, float *forces);
 __global__ void k_weighted_dx(const Dev *__restrict__ Sp, const double *w, float *dx);
 __global__ void k_check(const Dev *__restrict__ Sp, int mode, long long s, int omega, int nrep, long long nsamp,
-                        long long check_index, long long t_check, Status *st, int *donor, int *surv, long long *fec);
+                        long long check_index, long long t_check, Status *st, int *donor, int *surv, long long *fec,
+                        CycRec *cyc, int cycle);
+__global__ void k_zero_ints(int *p, int n);
 __global__ void k_clone(const Dev *__restrict__ Sp, const int *donor, int acc_mode);
 __global__ void k_init_vel(const Dev *__restrict__ Sp, float kT);
 __global__ void k_noise_test(uint32_t k0, uint32_t k1, int replica, long long step, int stream, int n,

@@ -1499,8 +1499,22 @@ __global__ void __launch_bounds__(1024) k_persist(PersistItem it)
 {
     int set, g;
     if (!persist_place(it, (int)blockIdx.x, set, g) || set + it.roff >= it.nrep) return;
-    persist_replica(*it.dev, it.sp.G, it.sp.lmax, it.sp.bnd[g], it.sp.bnd[g + 1], set + it.roff, g, it.s0, it.nsteps,
-                    it.t0, it.sample, it.state_end);
+    long long s0 = it.s0;
+    int t0 = it.t0;
+    if (it.cyc) {
+        // cycle of a captured run: nothing after the check that ended the call
+        if (it.cyc->halt_cycle < it.cycle) return;
+        const long long first = (long long)it.cycle * it.nsteps;
+        s0 = it.cyc->s_start + first;
+        t0 = (int)((it.cyc->t_start + first) % it.dev->t_gr);
+    }
+    persist_replica(*it.dev, it.sp.G, it.sp.lmax, it.sp.bnd[g], it.sp.bnd[g + 1], set + it.roff, g, s0, it.nsteps,
+                    t0, it.sample, it.state_end);
+}
+
+__global__ void __launch_bounds__(256) k_zero_ints(int *p, int n)
+{
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) p[k] = 0;
 }
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -1696,7 +1710,7 @@ __device__ void vote_block(int R, Fec fec, long long t_check, long long *red, lo
 // donor's observable sums (cleared when every worker is re-copied from the reference).
 __global__ void __launch_bounds__(256) k_check(const Dev *__restrict__ Sp, int mode, long long s, int omega, int nrep,
                                                long long nsamp, long long check_index, long long t_check, Status *st,
-                                               int *donor, int *surv, long long *fec)
+                                               int *donor, int *surv, long long *fec, CycRec *cyc, int cycle)
 {
     const Dev &S = *Sp;
     const int tid = threadIdx.x;
@@ -1704,9 +1718,23 @@ __global__ void __launch_bounds__(256) k_check(const Dev *__restrict__ Sp, int m
     __shared__ int wsum[16];
     __shared__ long long red[32];
     __shared__ int sh_ne;
+    __shared__ double rh_l[MAX_OBS];
     const int *state = S.state;
     auto ex = [&](int q) { return state[q] != omega; };
     const bool head = blockIdx.x == 0 && r == 0;
+    long long t_now = 0;                                   // cycle mode: steps of the call at this check
+    if (cyc) {
+        // cycle `cycle` of a captured run: its step, check index and status slot; nothing after
+        // the check that ended the call
+        if (cyc->halt_cycle < cycle) return;
+        omega = cyc->omega;
+        const long long after = (long long)(cycle + 1) * cyc->nsteps;
+        s = cyc->s_start + after;
+        check_index = cyc->M_start + cycle + 1;
+        t_now = cyc->t_start + after;
+        st += cycle;
+        if (head) nsamp = cyc->nsamp + (t_now / S.t_gr - (t_now - cyc->nsteps) / S.t_gr);
+    }
     if (mode == CHK_DEPHASE) {
         if (state[0] != omega) {
             // the reference walker left Omega: nothing is branched
@@ -1715,6 +1743,7 @@ __global__ void __launch_bounds__(256) k_check(const Dev *__restrict__ Sp, int m
                 st->M = 0; st->tau = 0; st->to_state = state[0];
                 for (int e = 0; e < 4; ++e) st->err[e] = S.err[e];
                 for (int j = 0; j < MAX_OBS; ++j) st->rhat[j] = __longlong_as_double(0x7FF0000000000000LL);
+                if (cyc) { cyc->nsamp = nsamp; cyc->halt_cycle = cycle; }
             }
             return;
         }
@@ -1786,7 +1815,26 @@ __global__ void __launch_bounds__(256) k_check(const Dev *__restrict__ Sp, int m
                 auto s2 = [&](int k) { return S.acc[((size_t)src(k) * MAX_OBS + j) * 2 + 1]; };
                 rh = rhat_wave(nrep - 1, nsamp, s1, s2);
             }
-            if ((tid & 63) == 0) st->rhat[j] = rh;
+            if ((tid & 63) == 0) { st->rhat[j] = rh; rh_l[j] = rh; }
+        }
+    }
+    if (cyc) {
+        // the decision the host takes from the status, taken here so that the later cycles of
+        // the run know whether to run: converged (Eq. 4 test, with the samples restarted when
+        // every worker was re-copied) or a first exit in the parallel step
+        __syncthreads();
+        if (tid == 0) {
+            bool halt = false;
+            if (mode == CHK_DEPHASE) {
+                const long long nafter = (ns == 0 && nrep > 1) ? 0 : nsamp;
+                bool conv = t_now >= S.t_min && nafter >= 2;
+                for (int j = 0; j < S.nobs && conv; ++j) conv = rh_l[j] < 1.0 + S.tol;
+                cyc->nsamp = nafter;
+                halt = conv;
+            } else if (mode == CHK_PARALLEL) {
+                halt = vk > 0;
+            }
+            if (halt) cyc->halt_cycle = cycle;
         }
     }
 }

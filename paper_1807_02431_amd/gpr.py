@@ -119,6 +119,7 @@ SIGNATURES = {
     "gpr_dephase_fixed": (C.c_int32, [_VP, C.c_int64, C.c_int64, C.POINTER(_Dephase)]),
     "gpr_autotune": (C.c_int32, [_VP, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "gpr_set_graph": (C.c_int32, [_VP, C.c_int32]),
+    "gpr_set_cycles": (C.c_int32, [_VP, C.c_int32]),
     "gpr_batch_advance": (C.c_int32, [C.POINTER(_VP), C.c_int32, C.c_int64, C.POINTER(_P64)]),
     "gpr_batch_run": (C.c_int32, [C.POINTER(_VP), C.c_int32, C.POINTER(_BatchOp)]),
     "gpr_set_params": (C.c_int32, [_VP, _PD, _PD, _PD, _PD]),
@@ -281,6 +282,10 @@ class System:
 
     def set_graph(self, cycle_steps):
         self._c(lib().gpr_set_graph(self._h, int(cycle_steps)))
+
+    def set_cycles(self, cycles):
+        """Convergence and parallel steps as replays of `cycles` captured check cycles (0: off)."""
+        self._c(lib().gpr_set_cycles(self._h, int(cycles)))
 
     def autotune(self, nsteps=200):
         """Times the persistent path's launch shapes and keeps the fastest; returns it."""

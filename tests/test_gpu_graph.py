@@ -88,3 +88,75 @@ def test_set_graph_refuses_bad_cycles():
         with pytest.raises(gpr.GprError) as e:
             g.set_graph(bad)
         assert e.value.code == -1
+
+
+def _rl300_flipping():
+    """The 300-atom receptor-ligand system with its state split at the current value of a
+    ligand dihedral, so that exits come within a few checks, and a tolerance that R-hat meets
+    at the first check, so that parallel steps follow."""
+    import oracle
+    rl = G.config("rl300", n_replicas=8, t_check=200, tol=1e9)
+    L = rl["n_atoms"] - 32 + 10
+    dih = [L, L + 1, L + 2, L + 3]
+    o = oracle.System(dict(rl, n_replicas=2, obs=[dict(kind=G.OBS_DIHEDRAL, atoms=dih)]))
+    phi0 = o.observables_of(rl["pos"], np.zeros((3, rl["n_atoms"])), 0.0)[0]
+    rl["state"] = dict(kind=G.STATE_DIHEDRAL_BOXES, atoms=dih + dih,
+                       boxes=[[-4.0, phi0 + 0.05, -4.0, 4.0], [phi0 + 0.05, 4.0, -4.0, 4.0]])
+    return rl
+
+
+@pytest.mark.parametrize("name,groups,cycles", [("toy", 1, 8), ("toy", 1, 1), ("rl300", 2, 4)])
+def test_check_cycles_match_host_checks(name, groups, cycles):
+    """Convergence and parallel steps as replays of captured check cycles (gpr_set_cycles): the
+    loop of Fig. 1 gives the same events, clock, branch and sample counts, R-hat bits and
+    configurations as with one host round trip per check; with two workgroups per replica the
+    captured persistent launches are cooperative."""
+    gpr = _gpr()
+    if name == "toy":
+        spec = dict(G.toy2d(n_replicas=64, seed=9), pos=np.array([[-0.2], [0.0], [0.0]]))
+        t_corr, n = 100, 6
+    else:
+        spec = _rl300_flipping()
+        t_corr, n = 400, 4
+    R = spec["n_replicas"]
+    say("check cycles", name, "groups", groups, "cycles", cycles)
+    a = gpr.System(spec, path=gpr.PATH_PERSISTENT)
+    b = gpr.System(spec, path=gpr.PATH_PERSISTENT)
+    if groups > 1:
+        a.set_launch(0, groups)
+        b.set_launch(0, groups)
+    a.set_cycles(cycles)
+
+    def loop(s):
+        out = []
+        while len(out) < n:
+            rc, ev = s.decorrelate(t_corr)
+            assert rc == 0
+            if ev["kind"] == 1:
+                out.append(("t", ev["from_state"], ev["to_state"], ev["steps_taken"]))
+                continue
+            rc, d = s.dephase()
+            assert rc == 0
+            out.append(("f", d["outcome"], d["to_state"], d["t_steps"], d["n_branch"], d["n_samples"],
+                        tuple(np.asarray(d["rhat"]).view(np.uint64).tolist())))
+            if d["outcome"] == 1:
+                continue
+            rc, e = s.parallel_step()
+            assert rc == 0
+            out.append(("p", e["M"], e["k"], e["tau_steps"], e["to_state"]))
+        return out
+    la, lb = loop(a), loop(b)
+    say(la)
+    assert la == lb
+    assert any(x[0] == "p" for x in la)
+    assert a.simulated_steps() == b.simulated_steps() and a.global_step() == b.global_step()
+    _same_state(a, b, R)
+    _same_acc(a, b)
+    # budgets that stop inside a replay's span fall back to host checks, and resume
+    rc, _ = a.decorrelate(0)
+    rc, _ = b.decorrelate(0)
+    if a.current_state() != -1:
+        ra, da = a.dephase(max_steps=3 * spec["t_check_dephase"] + 1)
+        rb, db = b.dephase(max_steps=3 * spec["t_check_dephase"] + 1)
+        assert ra == rb and (ra == 1 or da == db)
+        _same_state(a, b, R)
