@@ -322,6 +322,57 @@ def small_configs_bench(seconds=2.0):
     return out
 
 
+def _parrep_loop(s, n_exits, t_corr):
+    """The loop of Fig. 1 (transient step, convergence step, parallel step) until n_exits exit
+    events; returns the number of events."""
+    events = 0
+    while events < n_exits:
+        rc, ev = s.decorrelate(t_corr)
+        if ev["kind"] == 1:
+            events += 1
+            continue
+        rc, d = s.dephase()
+        if d["outcome"] == 1:
+            events += 1
+            continue
+        s.parallel_step()
+        events += 1
+    return events
+
+
+def toy_parrep_bench(n_exits=40):
+    """The Gen.ParRep loop on the toy (8 replicas, exit checks every 10 steps) on the persistent
+    path with one host round trip per check, and with check cycles replayed from a captured
+    graph (64 cycles per replay), beside the oracle: exit events and simulated steps per second
+    of wall time."""
+    import torch
+    import gpr_synth as G
+    import oracle
+    import paper_1807_02431_amd as gpr
+    out = {}
+    for label, cycles in (("host_checks", 0), ("graph_cycles_64", 64)):
+        s = gpr.System(G.toy2d(seed=17), path=gpr.PATH_PERSISTENT, stream=torch.cuda.current_stream())
+        s.set_cycles(cycles)
+        _parrep_loop(s, 3, 100)
+        torch.cuda.synchronize()
+        t0, st0 = time.perf_counter(), s.simulated_steps()
+        _parrep_loop(s, n_exits, 100)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[label] = dict(events_per_s=n_exits / dt, simulated_steps_per_s=(s.simulated_steps() - st0) / dt,
+                          seconds=dt)
+        s.close()
+    o = oracle.System(G.toy2d(seed=17))
+    _parrep_loop(o, 3, 100)
+    t0, st0 = time.perf_counter(), o.simulated_steps()
+    _parrep_loop(o, n_exits, 100)
+    dt = time.perf_counter() - t0
+    out["oracle_one_core"] = dict(events_per_s=n_exits / dt, simulated_steps_per_s=(o.simulated_steps() - st0) / dt,
+                                  seconds=dt)
+    out["exits"] = n_exits
+    return out
+
+
 def batching_bench(steps):
     """The uneven mix (22 / 300 / 1,200 / 2,432 atoms x 192 replicas) advanced in shared
     persistent launches, against the same systems advanced one after the other."""
@@ -458,6 +509,7 @@ def main():
     if not args.no_small:
         print("# toy and 22-atom chain", file=sys.stderr, flush=True)
         small = small_configs_bench()
+        small["toy_gen_parrep"] = toy_parrep_bench()
 
     cpu = None if args.no_cpu else cpu_baseline(spec)
     if cpu is not None:

@@ -46,34 +46,26 @@ __device__ __forceinline__ float3 neg3(float3 f) { return make_float3(-f.x, -f.y
 // ------------------------------------------------------------------ bonded terms of an atom range
 // Terms touching atoms [a0, a1), by kind (bond, angle, torsion, restraint, 1-4).  Terms are
 // sorted by their smallest atom and span at most `span` atoms, so those touching [a0, a1) have
-// their smallest atom in [a0 - span, a1).  A plan takes them all (PLAN_ALL), only those lying
-// inside [a0, a1) for sure, smallest atom in [a0, a1 - span) (PLAN_INNER), or the rest
-// (PLAN_EDGE: smallest atom in [a0 - span, a0) or [max(a0, a1 - span), a1)).  Of kind k the
-// entries [lo[k], lo[k] + n1[k]) and [lo2[k], lo2[k] + cnt[k] - n1[k]) occupy the slots
-// [off[k], off[k] + cnt[k]) of one flat index space in which every kind starts at a multiple
-// of 64 (so a wave sees one kind).
-constexpr int PLAN_ALL = 0, PLAN_INNER = 1, PLAN_EDGE = 2;
+// their smallest atom in [a0 - span, a1): of kind k the entries [lo[k], lo[k] + cnt[k]).  They
+// occupy the slots [off[k], off[k] + cnt[k]) of one flat index space in which every kind starts
+// at a multiple of 64 (so a wave sees one kind).
 struct BondedPlan {
-    int lo[5], n1[5], lo2[5], cnt[5], off[6];
+    int lo[5], cnt[5], off[6];
 };
 
-__device__ __forceinline__ BondedPlan bonded_plan(const Dev &S, int a0, int a1, int part = PLAN_ALL)
+__device__ __forceinline__ BondedPlan bonded_plan(const Dev &S, int a0, int a1)
 {
     const Topo &T = S.tp;
     BondedPlan bp;
     auto range = [&](int k, int nterm, const int *start, int span) {
-        int lo = 0, n1 = 0, lo2 = 0, n2 = 0;
+        int lo = 0, n = 0;
         if (nterm) {
             const GPR_GLOBAL int *st = gconst(start);
-            const int b0 = st[max(0, a0 - span)], b1 = st[a0], b2 = st[max(a0, a1 - span)], b3 = st[a1];
-            if (part == PLAN_ALL) { lo = b0; n1 = b3 - b0; }
-            else if (part == PLAN_INNER) { lo = b1; n1 = b2 - b1; }
-            else { lo = b0; n1 = b1 - b0; lo2 = b2; n2 = b3 - b2; }
+            lo = st[max(0, a0 - span)];
+            n = st[a1] - lo;
         }
         bp.lo[k] = lo;
-        bp.n1[k] = n1;
-        bp.lo2[k] = lo2;
-        bp.cnt[k] = n1 + n2;
+        bp.cnt[k] = n;
     };
     range(0, T.nb, T.b_start, T.b_span);
     range(1, T.na, T.a_start, T.a_span);
@@ -115,14 +107,14 @@ __device__ void bonded_range(const Dev &S, const BondedPlan &bp, const Pos &pos,
             // kind and topology index of the slot (static indices into the plan: no scratch)
             int k = -1, t = 0;
             if (slot < total) {
-                int local, cnt, lo, n1, lo2;
-                if (slot < bp.off[1]) { k = 0; local = slot; cnt = bp.cnt[0]; lo = bp.lo[0]; n1 = bp.n1[0]; lo2 = bp.lo2[0]; }
-                else if (slot < bp.off[2]) { k = 1; local = slot - bp.off[1]; cnt = bp.cnt[1]; lo = bp.lo[1]; n1 = bp.n1[1]; lo2 = bp.lo2[1]; }
-                else if (slot < bp.off[3]) { k = 2; local = slot - bp.off[2]; cnt = bp.cnt[2]; lo = bp.lo[2]; n1 = bp.n1[2]; lo2 = bp.lo2[2]; }
-                else if (slot < bp.off[4]) { k = 3; local = slot - bp.off[3]; cnt = bp.cnt[3]; lo = bp.lo[3]; n1 = bp.n1[3]; lo2 = bp.lo2[3]; }
-                else { k = 4; local = slot - bp.off[4]; cnt = bp.cnt[4]; lo = bp.lo[4]; n1 = bp.n1[4]; lo2 = bp.lo2[4]; }
+                int local, cnt, lo;
+                if (slot < bp.off[1]) { k = 0; local = slot; cnt = bp.cnt[0]; lo = bp.lo[0]; }
+                else if (slot < bp.off[2]) { k = 1; local = slot - bp.off[1]; cnt = bp.cnt[1]; lo = bp.lo[1]; }
+                else if (slot < bp.off[3]) { k = 2; local = slot - bp.off[2]; cnt = bp.cnt[2]; lo = bp.lo[2]; }
+                else if (slot < bp.off[4]) { k = 3; local = slot - bp.off[3]; cnt = bp.cnt[3]; lo = bp.lo[3]; }
+                else { k = 4; local = slot - bp.off[4]; cnt = bp.cnt[4]; lo = bp.lo[4]; }
                 if (local >= cnt) k = -1;
-                t = local < n1 ? lo + local : lo2 + (local - n1);
+                t = lo + local;
             }
             kind[u] = k;
             idx[u] = make_int4(0, 0, 0, 0);
@@ -1224,11 +1216,13 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
     const int t_gr = S.t_gr, need_energy = S.need_energy, cutoff_on = S.cutoff_on, period = S.period;
     const float half_skin2 = S.half_skin2;
     int *const errp = S.err;
-    // with several groups the bonded terms inside the group's range run while its first waves
-    // wait at the barrier and fetch the other groups' positions; the rest run after
+    // with several groups the first waves wait at the barrier and fetch the other groups'
+    // positions while the force accumulators are cleared
     const bool split = G > 1 && !toy && BT >= 128;
-    const BondedPlan bplan = bonded_plan(S, a0, a1, split ? PLAN_EDGE : PLAN_ALL);
-    const BondedPlan bpin = bonded_plan(S, a0, a1, PLAN_INNER);
+    // the bonded terms touching the group's atoms, on its last (up to) eight waves: their
+    // topology loads wait on memory, and the other waves meanwhile start the pair tasks
+    const BondedPlan bplan = bonded_plan(S, a0, a1);
+    const int nwv = BT >> 6, nbw = min(nwv, 8), bw0 = nwv - nbw;
     const int XT = BT >= 512 ? 128 : 64;                    // exchange threads (whole waves)
     long long *eacc = red + MAX_OBS * 8;
     bool alive = true;
@@ -1273,7 +1267,7 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
             if (g == 0 && tid == 0) __hip_atomic_store(sync + 16 + 16 * (int)((s + 1) % 3), 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (split) {
                 // arrive; the first XT threads wait (bounded spin, one per wave) and fetch the
-                // other groups' positions while the others add the inner bonded terms
+                // other groups' positions
                 asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
                 __syncthreads();                     // own positions stored, forces read
                 if (tid == 0) {
@@ -1316,8 +1310,6 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
                             if (a < n && (a < a0 || a >= a1)) { xs[a].x = xy[u].x; xs[a].y = xy[u].y; xs[a].z = z[u]; }
                         }
                     }
-                } else {
-                    bonded_range<PosLDS, 2>(S, bpin, PosLDS{xs}, a0, a1, fa, lmax, energy ? eacc : nullptr, tid - XT, BT - XT);
                 }
                 __syncthreads();
                 alive = bbuf != 0;
@@ -1374,9 +1366,11 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
                 if (energy) *eacc = fix_f(u);
             }
         } else {
-            // bonded terms, then the pair loop, whose tasks (16 atoms each, longest lists first)
-            // the waves take from a shared counter as they come free
-            bonded_range<PosLDS, 2>(S, bplan, PosLDS{xs}, a0, a1, fa, lmax, energy ? eacc : nullptr, tid, BT);
+            // bonded terms on the last waves, then the pair loop, whose tasks (16 atoms each,
+            // longest lists first) the waves take from a shared counter as they come free
+            if ((tid >> 6) >= bw0)
+                bonded_range<PosLDS, 2>(S, bplan, PosLDS{xs}, a0, a1, fa, lmax, energy ? eacc : nullptr, tid - bw0 * 64,
+                                        nbw * 64);
             const int ntask = nslot >> 4;
             const NbConsts nbk = nb_consts(S);
             for (;;) {
