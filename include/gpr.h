@@ -200,8 +200,9 @@ typedef struct gpr_exit_out {
 /* ---------------------------------------------------------------- lifecycle */
 /* Validates d, copies every array, uploads to the current HIP device, builds the pair lists
  * and evaluates F(q0) for all replicas (all replicas start as copies of (pos, vel)).
- * On failure *out is set to NULL.  EINVAL for malformed descriptors (including an
- * exclusion or 1-4 pair whose atom indices differ by more than 32). */
+ * On failure *out is set to NULL.  EINVAL for malformed descriptors.  Excluded and 1-4
+ * pairs may join any two atoms (rings, branches): those less than 32 indices apart are held
+ * as a bit mask per atom, the others in a sorted partner list per atom. */
 gpr_status gpr_system_create(const gpr_system_desc *d, gpr_system **out);
 void       gpr_system_destroy(gpr_system *sys);
 /* Static-lifetime text of the last error on sys, or of the calling thread when sys is NULL. */

@@ -352,12 +352,48 @@ static gpr_status persist_item(gpr_system *S, int nrep, int bt, size_t lds, int 
     return GPR_OK;
 }
 
+// The layout of a persistent launch checked on the host before it runs, with the device's own
+// placement function: items cover the grid in order without overlap, every workgroup is group
+// g < G of a set < nsets, every (set, g) occurs once, the groups' atom ranges are ordered,
+// within the system and no longer than the LDS arrays (lmax), and the block size is whole waves.
+static gpr_status check_layout(gpr_system *S, const PersistBatch &pb, int nblocks, int bt, bool single)
+{
+    if (pb.nitems < 1 || pb.nitems > MAX_BATCH || bt < 64 || bt > 1024 || bt % 64) return fail(S, GPR_EDEVICE, "bad persistent launch shape");
+    int next = 0;
+    for (int k = 0; k < pb.nitems; ++k) {
+        const PersistItem &it = pb.it[k];
+        const Split &sp = it.sp;
+        if (it.boff != next || it.nsets < 1 || it.nrep < 1 || sp.G < 1 || sp.G > 8 || !it.dev)
+            return fail(S, GPR_EDEVICE, "persistent launch layout: item placement");
+        if (!single && k > 0 && pb.it[k - 1].boff >= it.boff) return fail(S, GPR_EDEVICE, "persistent launch layout: item order");
+        const int n = sp.bnd[sp.G];
+        if (sp.bnd[0] != 0) return fail(S, GPR_EDEVICE, "persistent launch layout: atom ranges");
+        for (int g = 0; g < sp.G; ++g)
+            if (sp.bnd[g] > sp.bnd[g + 1] || sp.bnd[g + 1] > n || sp.bnd[g + 1] - sp.bnd[g] > sp.lmax)
+                return fail(S, GPR_EDEVICE, "persistent launch layout: atom ranges");
+        std::vector<unsigned char> seen((size_t)it.nsets * sp.G, 0);
+        for (int local = 0; local < it.nsets * sp.G; ++local) {
+            int set = -1, g = -1;
+            if (!persist_place(it, local, set, g) || set < 0 || set >= it.nsets || g < 0 || g >= sp.G ||
+                seen[(size_t)set * sp.G + g]++)
+                return fail(S, GPR_EDEVICE, "persistent launch layout: workgroup placement");
+        }
+        next = it.boff + it.nsets * sp.G;
+    }
+    if (next != nblocks) return fail(S, GPR_EDEVICE, "persistent launch layout: grid size");
+    return GPR_OK;
+}
+
 // One item whose sets each take one replica (roff + set) runs k_persist; anything else
 // (several systems, or sets that take replicas in turn) runs k_persist_batch.
 static gpr_status launch_persist(gpr_system *S, PersistBatch &pb, int nblocks, int bt, size_t lds, bool coop,
                                  hipStream_t stream, bool one_round = false)
 {
     const bool single = pb.nitems == 1 && (one_round || pb.it[0].nsets >= pb.it[0].nrep);
+    {
+        const gpr_status rc = check_layout(S, pb, nblocks, bt, single);
+        if (rc) return rc;
+    }
     const void *fn = single ? (const void *)k_persist : (const void *)k_persist_batch;
     void *args_single[] = {(void *)&pb.it[0]};
     void *args_batch[] = {(void *)&pb};
@@ -627,26 +663,36 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
     HIPCHK(S, upload(S, (float **)&d.sd, sd));
     HIPCHK(S, upload(S, (float **)&d.mass, mass));
 
-    // exclusions (and 1-4 pairs) as bit masks over index offsets -32..31
+    // exclusions (and 1-4 pairs) as bit masks over index offsets -32..31, and those farther
+    // apart as an ascending partner list per atom
     std::vector<unsigned long long> excl(np, 0ull);
-    auto mark = [&](int i, int j) -> bool {
+    std::vector<std::vector<int>> far(n);
+    auto mark = [&](int i, int j) {
         const int off = j - i;
-        if (off < -32 || off >= 32 || off == 0) return off == 0;
-        excl[i] |= 1ull << (off + 32);
-        excl[j] |= 1ull << (-off + 32);
-        return true;
+        if (off == 0) return;
+        if (off > -32 && off < 32) {
+            excl[i] |= 1ull << (off + 32);
+            excl[j] |= 1ull << (-off + 32);
+        } else {
+            far[i].push_back(j);
+            far[j].push_back(i);
+        }
     };
     if (D->kind == GPR_KIND_MOLECULAR) {
-        for (int e = 0; e < D->n_exclusions; ++e)
-            if (!mark(D->exclusion_atoms[2 * e], D->exclusion_atoms[2 * e + 1]) ||
-                D->exclusion_atoms[2 * e + 1] - D->exclusion_atoms[2 * e] == 32)
-                return fail(S, GPR_EINVAL, "exclusion between atoms more than 32 indices apart");
-        for (int p = 0; p < D->n_pairs14; ++p)
-            if (!mark(D->pair14_atoms[2 * p], D->pair14_atoms[2 * p + 1]) ||
-                D->pair14_atoms[2 * p + 1] - D->pair14_atoms[2 * p] == 32)
-                return fail(S, GPR_EINVAL, "1-4 pair between atoms more than 32 indices apart");
+        for (int e = 0; e < D->n_exclusions; ++e) mark(D->exclusion_atoms[2 * e], D->exclusion_atoms[2 * e + 1]);
+        for (int p = 0; p < D->n_pairs14; ++p) mark(D->pair14_atoms[2 * p], D->pair14_atoms[2 * p + 1]);
     }
+    std::vector<int> far_start(n + 1, 0), far_j;
+    for (int i = 0; i < n; ++i) {
+        std::sort(far[i].begin(), far[i].end());
+        far[i].erase(std::unique(far[i].begin(), far[i].end()), far[i].end());
+        far_start[i + 1] = far_start[i] + (int)far[i].size();
+        far_j.insert(far_j.end(), far[i].begin(), far[i].end());
+    }
+    d.has_far = far_j.empty() ? 0 : 1;
     HIPCHK(S, upload(S, (unsigned long long **)&d.excl, excl));
+    HIPCHK(S, upload(S, (int **)&d.far_start, far_start));
+    HIPCHK(S, upload(S, (int **)&d.far_j, far_j));
 
     // replica state: every replica starts from (pos, vel)
     const size_t rs = (size_t)R * 3 * np;
@@ -1667,6 +1713,8 @@ static gpr_status cycle_graph(gpr_system *S, int op, hipGraphExec_t *out)
     gpr_status rc = persist_item(S, nrep, S->bt_persist, lds, -1, pb.it[0], nblocks, coop);
     if (rc) return rc;
     const int rounds = (nrep + pb.it[0].nsets - 1) / pb.it[0].nsets;
+    rc = check_layout(S, pb, nblocks, S->bt_persist, true);
+    if (rc) return rc;
     const dim3 cgrid = dep ? dim3((3 * S->np + 255) / 256, nrep) : dim3(1, 1);
     hipStream_t cs = nullptr;
     HIPCHK(S, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));

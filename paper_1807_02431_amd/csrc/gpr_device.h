@@ -81,6 +81,8 @@ struct Dev {
     const float *sd;                       // sqrt((1 - c1^2) kT / m)
     const float *mass;
     const unsigned long long *excl;        // bit (j - i + 32) set: pair excluded or 1-4
+    int has_far;                           // some excluded or 1-4 pair lies 32 or more indices apart:
+    const int *far_start, *far_j;          // [n + 1] offsets and ascending partners of those pairs
     float *x, *v, *xb;
     long long *F;
     long long *E;                          // [R] potential energy, fixed point

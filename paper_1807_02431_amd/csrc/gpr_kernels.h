@@ -68,6 +68,26 @@ struct PersistBatch {
     PersistItem it[MAX_BATCH];
 };
 
+// Work items of persistent launches: an item is a system whose replicas are shared by nsets
+// sets of sp.G workgroups.  Workgroup `local` of the item (counted from boff) is group g of set
+// `set`.  With xcd set (nsets a multiple of 8) the workgroups of a set have equal blockIdx mod
+// 8, i.e. sit on one XCD and share its L2.  Host code checks every launch's layout with it.
+__host__ __device__ inline bool persist_place(const PersistItem &it, int local, int &set, int &g)
+{
+    const int G = it.sp.G;
+    if (local < 0 || local >= it.nsets * G) return false;
+    if (G == 1) {
+        set = local; g = 0;
+    } else if (it.xcd) {
+        const int x = local % 8, slot = local / 8;
+        set = (slot / G) * 8 + x;
+        g = slot % G;
+    } else {
+        set = local / G; g = local % G;
+    }
+    return true;
+}
+
 __global__ void k_persist(PersistItem it);
 __global__ void k_persist_batch(PersistBatch pb);
 __global__ void k_grad_nb(const Dev *__restrict__ Sp, const double *w);

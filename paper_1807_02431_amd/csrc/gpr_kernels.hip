@@ -273,6 +273,11 @@ __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool v
     const int iw = __builtin_amdgcn_readfirstlane(i);
     // partners to drop: excluded and 1-4 pairs within +-32 of i, and i itself (bit 32)
     const unsigned long long ex = (valid ? gconst(S.excl)[i] : 0ull) | (1ull << 32);
+    // excluded and 1-4 partners farther than that: i's ascending list far_j[far_start[i] ..
+    // far_start[i + 1]), merged against the entries as they are emitted (also ascending)
+    int flo = 0, fhi = 0;
+    const GPR_GLOBAL int *fj = gconst(S.far_j);
+    if (S.has_far && valid) { flo = gconst(S.far_start)[i]; fhi = gconst(S.far_start)[i + 1]; }
     const int cap = 4 * S.Kg;
     GPR_GLOBAL unsigned long long *L =
         (GPR_GLOBAL unsigned long long *)gmut(S.nbl) + (size_t)r * S.Kg * stride + (size_t)(valid ? i : 0) * P + q;
@@ -309,6 +314,10 @@ __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool v
                 for (int e = 0; e < UNR; ++e) {
                     if (!has[e]) continue;
                     const unsigned j = (unsigned)(bk[e] * BLK + q + (k[e] % CPB) * P);
+                    if (flo < fhi) {
+                        while (flo < fhi && (unsigned)fj[flo] < j) ++flo;
+                        if (flo < fhi && (unsigned)fj[flo] == j) continue;
+                    }
                     if (cnt < cap) {
                         word = (word >> 16) | ((unsigned long long)j << 48);
                         if ((cnt & 3) == 3) {
@@ -1466,25 +1475,6 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
         const int id = state_wg(S, xs, red, &sbuf, tid, BT);
         if (tid == 0) S.state[r] = id;
     }
-}
-
-// Work items of persistent launches: an item is a system whose replicas are shared by nsets
-// sets of sp.G workgroups.  With xcd set (nsets a multiple of 8) the workgroups of a set have
-// equal blockIdx mod 8, i.e. sit on one XCD and share its L2.
-__device__ __forceinline__ bool persist_place(const PersistItem &it, int local, int &set, int &g)
-{
-    const int G = it.sp.G;
-    if (local < 0 || local >= it.nsets * G) return false;
-    if (G == 1) {
-        set = local; g = 0;
-    } else if (it.xcd) {
-        const int x = local % 8, slot = local / 8;
-        set = (slot / G) * 8 + x;
-        g = slot % G;
-    } else {
-        set = local / G; g = local % G;
-    }
-    return true;
 }
 
 // One system, one replica per set: replicas roff, roff + 1, ... (a system with more replicas

@@ -159,3 +159,60 @@ def test_overlapping_atoms_are_reported_unstable(path):
         g.advance(20)
     assert e.value.code == -5
     assert np.isfinite(g.get_state(0)[0]).all()
+
+
+def _scrambled_chain(n=64, R=4):
+    """A chain of the 22-atom workload's force field, n atoms long, whose atom indices are
+    permuted (chain atom k becomes atom 17 k mod n) so that neighbours along the chain sit 17 or
+    47 indices apart: its excluded and 1-4 pairs join atoms up to 51 indices apart (beyond the
+    per-atom bit mask), as in rings or branched molecules, while the geometry stays that of a
+    relaxed chain."""
+    spec = G.chain(seed=4, n_atoms=n, n_replicas=R)
+    new = (17 * np.arange(n)) % n
+    out = dict(spec)
+    for key in ("mass", "sigma", "epsilon", "charge"):
+        v = np.asarray(spec[key], np.float64)
+        w = np.empty_like(v)
+        w[new] = v
+        out[key] = w
+    pos = np.asarray(spec["pos"], np.float64)
+    out["pos"] = np.empty_like(pos)
+    out["pos"][:, new] = pos
+    for key in ("bonds", "angles", "torsions", "pairs14", "exclusions"):
+        out[key] = new[np.asarray(spec[key])].astype(np.int32)
+    st = dict(spec["state"])
+    st["atoms"] = [int(new[a]) for a in st["atoms"]]
+    out["state"] = st
+    obs = []
+    for o in spec["obs"]:
+        o = dict(o)
+        if "atoms" in o:
+            o["atoms"] = [int(new[a]) for a in o["atoms"]]
+        obs.append(o)
+    out["obs"] = obs
+    return G.round_to_f32(out)
+
+
+@pytest.mark.parametrize("path", [0, 1])
+def test_far_exclusions_match_oracle(path):
+    """Excluded and 1-4 pairs of a chain whose atom indices are scrambled lie up to 51 indices
+    apart (beyond the per-atom bit mask): forces and energies at the start and positions after
+    100 steps match the oracle, which excludes them by definition."""
+    gpr = _gpr()
+    spec = _scrambled_chain()
+    span = max(np.abs(np.diff(spec[k], axis=1)).max() for k in ("exclusions", "pairs14"))
+    assert span >= 32
+    say("scrambled chain, path", path)
+    g = gpr.System(spec, path=path)
+    o = oracle.System(spec)
+    Eg, Fg = g.energy_forces()
+    Eo, Fo = o.energy_forces()
+    for r in range(spec["n_replicas"]):
+        assert np.abs(Fg[r] - Fo[r]).max() < 1e-5 * np.abs(Fo[r]).max()
+        assert abs(Eg[r] - Eo[r]) <= 1e-5 * max(1.0, abs(Eo[r]))
+    g.advance(100)
+    o.step_replicas(100, 0, spec["n_replicas"])
+    for r in range(spec["n_replicas"]):
+        qg, _ = g.get_state(r)
+        qo, _ = o.get_state(r)
+        assert np.abs(qg - qo).max() < 1e-5 * np.abs(qo).max()
