@@ -134,10 +134,11 @@ def flops_per_replica_step(spec, pairs):
 
 
 def timed_advance(sysobj, steps):
+    """Wall time of gpr_advance over `steps` steps (first exit checks not read back)."""
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sysobj.advance(steps)
+    sysobj.advance(steps, first_exit=False)
     torch.cuda.synchronize()
     return time.perf_counter() - t0
 

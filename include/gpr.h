@@ -345,7 +345,8 @@ gpr_status gpr_set_state(gpr_system *sys, int32_t r, const double *q, const doub
  * handle since creation, so that several short calls sample and test as one long call
  * does.  first_exit_check ([R] host int64, or NULL) receives, per replica, the index
  * (1-based, counted over all calls) of the first check within this call at which
- * state != Omega (0 if none).  The fixed-work stepping loop of the measurement harness. */
+ * state != Omega (0 if none); with NULL they are neither recorded nor read back.  The
+ * fixed-work stepping loop of the measurement harness. */
 gpr_status gpr_advance(gpr_system *sys, int64_t nsteps, int64_t *first_exit_check);
 
 /* Steps taken by gpr_advance / gpr_batch_advance on the handle since creation (the position

@@ -74,6 +74,8 @@ struct gpr_system {
     Status *stc_dev = nullptr, *stc_host = nullptr;   // [cycles] statuses of a replay
     // scratch
     Status *st_dev = nullptr, *st_host = nullptr;
+    long long *adv_fec = nullptr;   // page-locked [R]: first exit checks read back by gpr_advance
+    int *adv_err = nullptr;         // page-locked [4]: error flags read back by gpr_advance
     double *obs_out = nullptr;
     int *donor = nullptr, *surv = nullptr;
     long long *fec = nullptr;
@@ -624,6 +626,8 @@ extern "C" void gpr_system_destroy(gpr_system *S)
     for (hipEvent_t e : S->ev_a) (void)hipEventDestroy(e);
     for (hipEvent_t e : S->ev_b) (void)hipEventDestroy(e);
     if (S->st_host) (void)hipHostFree(S->st_host);
+    if (S->adv_fec) (void)hipHostFree(S->adv_fec);
+    if (S->adv_err) (void)hipHostFree(S->adv_err);
     delete S;
 }
 
@@ -915,6 +919,8 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
     // scratch for the per-check bookkeeping
     HIPCHK(S, dalloc(S, &S->st_dev, 1));
     HIPCHK(S, hipHostMalloc((void **)&S->st_host, sizeof(Status), hipHostMallocDefault));
+    HIPCHK(S, hipHostMalloc((void **)&S->adv_fec, sizeof(long long) * R, hipHostMallocDefault));
+    HIPCHK(S, hipHostMalloc((void **)&S->adv_err, sizeof(int) * 4, hipHostMallocDefault));
     HIPCHK(S, dalloc(S, &S->donor, R));
     HIPCHK(S, dalloc(S, &S->surv, R));
     HIPCHK(S, dalloc(S, &S->fec, R));
@@ -1938,7 +1944,8 @@ extern "C" gpr_status gpr_advance(gpr_system *S, int64_t nsteps, int64_t *first_
 {
     if (!S) return fail(nullptr, GPR_EINVAL, "NULL system");
     if (nsteps < 0) return fail(S, GPR_EINVAL, "nsteps < 0");
-    HIPCHK(S, hipMemsetAsync(S->fec, 0, sizeof(long long) * S->R, S->stream));
+    // first exit checks are recorded (and read back) only for a caller that asks for them
+    if (first_exit_check) HIPCHK(S, hipMemsetAsync(S->fec, 0, sizeof(long long) * S->R, S->stream));
     // the sampling (every t_GR) and check (every t_check_dephase) schedule runs on the steps
     // counted over all calls, so that short calls sample and check as one long call would
     long long t = S->adv_t;
@@ -1956,16 +1963,17 @@ extern "C" gpr_status gpr_advance(gpr_system *S, int64_t nsteps, int64_t *first_
             if (rc) return rc;
         }
     }
-    std::vector<long long> f(S->R);
-    HIPCHK(S, hipMemcpyAsync(f.data(), S->fec, sizeof(long long) * S->R, hipMemcpyDeviceToHost, S->stream));
-    int err[4];
-    HIPCHK(S, hipMemcpyAsync(err, S->d.err, sizeof err, hipMemcpyDeviceToHost, S->stream));
+    // error flags (and first exit checks) through page-locked memory, one wait
+    if (first_exit_check)
+        HIPCHK(S, hipMemcpyAsync(S->adv_fec, S->fec, sizeof(long long) * S->R, hipMemcpyDeviceToHost, S->stream));
+    HIPCHK(S, hipMemcpyAsync(S->adv_err, S->d.err, sizeof(int) * 4, hipMemcpyDeviceToHost, S->stream));
     HIPCHK(S, hipStreamSynchronize(S->stream));
     HIPCHK(S, prof_collect(S));
+    const int *err = S->adv_err;
     if (err[ERR_UNSTABLE]) return fail(S, GPR_EUNSTABLE, "non-finite or overflowing state");
     if (err[ERR_LIST]) return fail(S, GPR_EDEVICE, "pair-list capacity exceeded");
     if (err[ERR_BARRIER]) return fail(S, GPR_EDEVICE, "persistent-kernel barrier timed out");
-    if (first_exit_check) for (int r = 0; r < S->R; ++r) first_exit_check[r] = f[r];
+    if (first_exit_check) for (int r = 0; r < S->R; ++r) first_exit_check[r] = S->adv_fec[r];
     return GPR_OK;
 }
 

@@ -394,7 +394,12 @@ class System:
         """Steps taken by advance / batch_advance since creation (their schedule's position)."""
         return lib().gpr_advance_steps(self._h)
 
-    def advance(self, nsteps):
+    def advance(self, nsteps, first_exit=True):
+        """gpr_advance; returns the first exit checks, or None with first_exit=False (then
+        they are not read back)."""
+        if not first_exit:
+            self._c(lib().gpr_advance(self._h, int(nsteps), None))
+            return None
         fec = np.zeros(self.R, np.int64)
         self._c(lib().gpr_advance(self._h, int(nsteps), fec.ctypes.data_as(_P64)))
         return fec
