@@ -57,21 +57,27 @@ __device__ __forceinline__ BondedPlan bonded_plan(const Dev &S, int a0, int a1)
 {
     const Topo &T = S.tp;
     BondedPlan bp;
-    auto range = [&](int k, int nterm, const int *start, int span) {
-        int lo = 0, n = 0;
-        if (nterm) {
-            const GPR_GLOBAL int *st = gconst(start);
-            lo = st[max(0, a0 - span)];
-            n = st[a1] - lo;
+    // a molecular system has all five start arrays (n + 1 entries each, all zero for a kind
+    // without terms) and the toy none: one branch, then the ten reads go out together instead
+    // of one dependent round trip per kind
+    if (S.kind == KIND_MOL) {
+        const int *const start[5] = {T.b_start, T.a_start, T.t_start, T.r_start, T.p_start};
+        const int span[5] = {T.b_span, T.a_span, T.t_span, 0, T.p_span};
+        int lo[5], hi[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            lo[k] = gconst(start[k])[max(0, a0 - span[k])];
+            hi[k] = gconst(start[k])[a1];
         }
-        bp.lo[k] = lo;
-        bp.cnt[k] = n;
-    };
-    range(0, T.nb, T.b_start, T.b_span);
-    range(1, T.na, T.a_start, T.a_span);
-    range(2, T.nt, T.t_start, T.t_span);
-    range(3, T.nr, T.r_start, 0);
-    range(4, T.n14, T.p_start, T.p_span);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            bp.lo[k] = lo[k];
+            bp.cnt[k] = hi[k] - lo[k];
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) bp.lo[k] = bp.cnt[k] = 0;
+    }
     bp.off[0] = 0;
 #pragma unroll
     for (int k = 0; k < 5; ++k) bp.off[k + 1] = bp.off[k] + (bp.cnt[k] + 63) / 64 * 64;
@@ -1225,14 +1231,13 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
     const int t_gr = S.t_gr, need_energy = S.need_energy, cutoff_on = S.cutoff_on, period = S.period;
     const float half_skin2 = S.half_skin2;
     int *const errp = S.err;
-    // with several groups the first waves wait at the barrier and fetch the other groups'
-    // positions while the force accumulators are cleared
+    // with several groups every wave waits at the barrier on its own and then takes its share
+    // of the other groups' positions: one round trip of device-coherent reads per step
     const bool split = G > 1 && !toy && BT >= 128;
     // the bonded terms touching the group's atoms, on its last (up to) eight waves: their
     // topology loads wait on memory, and the other waves meanwhile start the pair tasks
     const BondedPlan bplan = bonded_plan(S, a0, a1);
     const int nwv = BT >> 6, nbw = min(nwv, 8), bw0 = nwv - nbw;
-    const int XT = BT >= 512 ? 128 : 64;                    // exchange threads (whole waves)
     long long *eacc = red + MAX_OBS * 8;
     bool alive = true;
     bool pend = false;                                      // the previous step's closing B is due
@@ -1275,8 +1280,8 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
             if (hit) __hip_atomic_fetch_or(sync + 16 + 16 * (int)(s % 3), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (g == 0 && tid == 0) __hip_atomic_store(sync + 16 + 16 * (int)((s + 1) % 3), 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (split) {
-                // arrive; the first XT threads wait (bounded spin, one per wave) and fetch the
-                // other groups' positions
+                // arrive; each wave waits (bounded spin by its first lane), then all threads
+                // fetch the other groups' positions
                 asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
                 __syncthreads();                     // own positions stored, forces read
                 if (tid == 0) {
@@ -1287,37 +1292,35 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
                 if (tid == 0) { *eacc = 0; ptask = 0; }
                 __syncthreads();
                 const int target = G * ++gen;
-                if (tid < XT) {
-                    if ((tid & 63) == 0) {
-                        int spins = 0;
-                        while (__hip_atomic_load(sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                            if (++spins > SPIN_MAX) {
-                                atomicOr(errp + ERR_BARRIER, 1);
-                                bbuf = 0;
-                                break;
-                            }
-                            __builtin_amdgcn_s_sleep(1);
+                if ((tid & 63) == 0) {
+                    int spins = 0;
+                    while (__hip_atomic_load(sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                        if (++spins > SPIN_MAX) {
+                            atomicOr(errp + ERR_BARRIER, 1);
+                            bbuf = 0;
+                            break;
                         }
+                        __builtin_amdgcn_s_sleep(1);
                     }
-                    __builtin_amdgcn_wave_barrier();
-                    if (tid == 0) hbuf = __hip_atomic_load(sync + 16 + 16 * (int)(s % 3), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    // all loads of a batch in flight before the first LDS write
-                    constexpr int XU = 4;
-                    for (int a0x = 0; a0x < n; a0x += XU * XT) {
-                        float2 xy[XU];
-                        float z[XU];
+                }
+                __builtin_amdgcn_wave_barrier();
+                if (tid == 0) hbuf = __hip_atomic_load(sync + 16 + 16 * (int)(s % 3), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // all loads of a batch in flight before the first LDS write
+                constexpr int XU = 4;
+                for (int a0x = 0; a0x < n; a0x += XU * BT) {
+                    float2 xy[XU];
+                    float z[XU];
 #pragma unroll
-                        for (int u = 0; u < XU; ++u) {
-                            const int a = a0x + u * XT + tid;
-                            const bool other = a < n && (a < a0 || a >= a1);
-                            xy[u] = other ? ld_coh2(xch_xy + a) : make_float2(0.f, 0.f);
-                            z[u] = other ? ld_coh(xch_z + a) : 0.f;
-                        }
+                    for (int u = 0; u < XU; ++u) {
+                        const int a = a0x + u * BT + tid;
+                        const bool other = a < n && (a < a0 || a >= a1);
+                        xy[u] = other ? ld_coh2(xch_xy + a) : make_float2(0.f, 0.f);
+                        z[u] = other ? ld_coh(xch_z + a) : 0.f;
+                    }
 #pragma unroll
-                        for (int u = 0; u < XU; ++u) {
-                            const int a = a0x + u * XT + tid;
-                            if (a < n && (a < a0 || a >= a1)) { xs[a].x = xy[u].x; xs[a].y = xy[u].y; xs[a].z = z[u]; }
-                        }
+                    for (int u = 0; u < XU; ++u) {
+                        const int a = a0x + u * BT + tid;
+                        if (a < n && (a < a0 || a >= a1)) { xs[a].x = xy[u].x; xs[a].y = xy[u].y; xs[a].z = z[u]; }
                     }
                 }
                 __syncthreads();
