@@ -406,6 +406,48 @@ def batching_bench(steps):
                 separate_replica_steps_per_s=reps * steps / ts, speedup_vs_separate=ts / tb)
 
 
+def phases_bench(lengths=(1000, 20), launches=(3, 50), warmup=300):
+    """Per-phase time of the persistent kernel from the timer build of the library (the same
+    sources with per-phase clocks, loaded in place of the product one; results unchanged):
+    for each launch length, µs per step in each phase averaged over every (replica, group),
+    the launch prologue and epilogue per launch, pair-list rebuilds per step, and the sum of
+    the phases of the slowest group against the kernel's own event timing."""
+    import gpr_synth as G
+    import paper_1807_02431_amd.gpr as gb
+    gb.use_probe_library()
+    import torch
+    spec = G.config("rl2432")
+    s = gb.System(spec, path=gb.PATH_PERSISTENT, stream=torch.cuda.current_stream())
+    s.advance(warmup, first_exit=False)
+    s.phase_read()
+    out = {}
+    for L, nl in zip(lengths, launches):
+        s.profile(True)
+        for _ in range(nl):
+            s.advance(L, first_exit=False)
+        kms, kn = s.profile_read()
+        s.profile(False)
+        ph = s.phase_read()                                   # [R, 8, 9]
+        live = ph[:, :, 7] > 0                                 # (replica, group) slots that ran
+        steps = ph[:, :, 7][live].mean()
+        kn = max(kn, 1)                                        # kernel launches (a call that
+        per = {}                                               # crosses a check boundary takes two)
+        for k, name in enumerate(gb.PHASES):
+            v = ph[:, :, k][live]
+            if name in ("prologue", "epilogue"):
+                per[name + "_us_per_launch"] = float(v.mean() / kn)
+            else:
+                per[name + "_us_per_step"] = float(v.mean() / steps)
+        tot = ph[:, :, :7].sum(axis=2)[live]
+        out["calls_of_%d_steps" % L] = dict(
+            calls=nl, kernel_launches=kn, steps_per_group=float(steps),
+            rebuilds_per_step=float(ph[:, :, 8][live].mean() / steps),
+            kernel_us_per_launch=1000.0 * kms / kn,
+            phases_sum_us_per_launch_mean=float(tot.mean() / kn),
+            phases_sum_us_per_launch_max_group=float(tot.max() / kn), **per)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -420,12 +462,18 @@ def main():
     ap.add_argument("--no-small", action="store_true", help="skip the toy and 22-atom chain measurements")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 256 MiB device-to-device copy (calibrates HBM byte counters)")
+    ap.add_argument("--phases", action="store_true",
+                    help="only measure the persistent kernel's phases with the timer build of the library")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the replicas of one system share one device "
               "(sharding replicas over several GPUs is not implemented); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+    if args.phases:
+        print(json.dumps({"phases": phases_bench(), "workload": "rl2432 x 64, persistent path",
+                          "source_sha256": kernel_source_hash()}))
+        return
 
     # the oracle on all host cores first, while this process has not touched the GPU
     cpu_all = None

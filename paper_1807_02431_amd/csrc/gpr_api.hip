@@ -45,6 +45,9 @@ struct gpr_system {
     std::vector<int2> p14_h;
     double scale14 = 0.0;
     int max_coresident = 0;    // persistent-kernel workgroups that fit on the device at once
+    int cap_bt = -1;           // persist_capacity: the launch shape last asked for and its capacity
+    size_t cap_lds = 0;
+    int cap_blocks = 0;
     int n = 0, R = 0, np = 0, kind = 0, nobs = 0;
     int t_gr = 1, tcd = 1, tcp = 1;
     double tol = 0, dt = 0, kT = 0;
@@ -314,12 +317,34 @@ static gpr_status launch_forces(gpr_system *S, int r_off, int nrep, long long s,
 
 // advances replicas [0, nrep) by nsteps from local step counter t0; sample: accumulate the
 // observables of workers every t_gr; state_end: state ids at the end
-// Workgroup sets of one system in a persistent launch.  One workgroup per replica needs no
-// co-residency (normal launch, one workgroup per replica); G > 1 workgroups per replica
-// synchronise, so all workgroups of the launch must be resident together (cooperative launch)
-// and the replicas are shared by at most capacity / G sets (cap_blocks < 0: the whole device).
+// Workgroups of the persistent kernel that the device holds at once for (bt, lds): the
+// occupancy query, kept per system for the last launch shape asked for.
+static gpr_status persist_capacity(gpr_system *S, int bt, size_t lds, int &cap)
+{
+    if (S->cap_bt != bt || S->cap_lds != lds) {
+        int dev = 0, cus = 0, per_cu = 0;
+        HIPCHK(S, hipGetDevice(&dev));
+        HIPCHK(S, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        HIPCHK(S, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_persist, bt, lds));
+        S->cap_bt = bt;
+        S->cap_lds = lds;
+        S->cap_blocks = per_cu * cus;
+    }
+    cap = S->cap_blocks;
+    return GPR_OK;
+}
+
+// Workgroup sets of one system in a persistent launch.  With G > 1 workgroups per replica the
+// groups of a replica wait for each other, so they must be resident together: the replicas are
+// shared by at most capacity / G sets (cap_blocks < 0: the whole device), so that the grid is
+// no larger than what the device holds at once, and every workgroup gets a CU as soon as the
+// device is free of other work.  (A launch cannot start its workgroups while other kernels
+// hold the CUs they need only until those kernels end; should a group still wait longer than
+// the barrier's bounded spin, the call reports GPR_EDEVICE, never hangs.)  No cooperative
+// launch: it adds tens of microseconds to each launch and is refused while another process
+// holds the device's cooperative resources.
 static gpr_status persist_item(gpr_system *S, int nrep, int bt, size_t lds, int cap_blocks, PersistItem &it,
-                               int &nblocks, bool &coop)
+                               int &nblocks)
 {
     const int G = S->groups;
     it = PersistItem{};
@@ -331,15 +356,11 @@ static gpr_status persist_item(gpr_system *S, int nrep, int bt, size_t lds, int 
         it.nsets = nrep;
         it.xcd = 0;
         nblocks = nrep;
-        coop = false;
         return GPR_OK;
     }
     if (cap_blocks < 0) {
-        int dev = 0, cus = 0, per_cu = 0;
-        HIPCHK(S, hipGetDevice(&dev));
-        HIPCHK(S, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        HIPCHK(S, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_persist, bt, lds));
-        cap_blocks = per_cu * cus;
+        const gpr_status rc = persist_capacity(S, bt, lds, cap_blocks);
+        if (rc) return rc;
     }
     int nsets = std::min(nrep, cap_blocks / G);
     if (nsets < 1) return fail(S, GPR_EINVAL, "a replica's workgroups do not fit on the device at once");
@@ -350,7 +371,6 @@ static gpr_status persist_item(gpr_system *S, int nrep, int bt, size_t lds, int 
     }
     it.nsets = nsets;
     nblocks = nsets * G;
-    coop = true;
     return GPR_OK;
 }
 
@@ -388,7 +408,7 @@ static gpr_status check_layout(gpr_system *S, const PersistBatch &pb, int nblock
 
 // One item whose sets each take one replica (roff + set) runs k_persist; anything else
 // (several systems, or sets that take replicas in turn) runs k_persist_batch.
-static gpr_status launch_persist(gpr_system *S, PersistBatch &pb, int nblocks, int bt, size_t lds, bool coop,
+static gpr_status launch_persist(gpr_system *S, PersistBatch &pb, int nblocks, int bt, size_t lds,
                                  hipStream_t stream, bool one_round = false)
 {
     const bool single = pb.nitems == 1 && (one_round || pb.it[0].nsets >= pb.it[0].nrep);
@@ -400,11 +420,7 @@ static gpr_status launch_persist(gpr_system *S, PersistBatch &pb, int nblocks, i
     void *args_single[] = {(void *)&pb.it[0]};
     void *args_batch[] = {(void *)&pb};
     void **args = single ? args_single : args_batch;
-    if (!coop) {
-        HIPCHK(S, hipLaunchKernel(fn, dim3(nblocks), dim3(bt), args, lds, stream));
-    } else {
-        HIPCHK(S, hipLaunchCooperativeKernel(fn, dim3(nblocks), dim3(bt), args, (unsigned)lds, stream));
-    }
+    HIPCHK(S, hipLaunchKernel(fn, dim3(nblocks), dim3(bt), args, lds, stream));
     return GPR_OK;
 }
 
@@ -502,9 +518,8 @@ static gpr_status run_steps(gpr_system *S, int nrep, long long nsteps, long long
         PersistBatch pb{};
         pb.nitems = 1;
         int nblocks = 0;
-        bool coop = false;
         const size_t lds = persist_lds(S->n, S->np, S->split);
-        gpr_status rc = persist_item(S, nrep, S->bt_persist, lds, -1, pb.it[0], nblocks, coop);
+        gpr_status rc = persist_item(S, nrep, S->bt_persist, lds, -1, pb.it[0], nblocks);
         if (rc) return rc;
         // more replicas than sets that fit at once: rounds of launches, each set taking one
         // replica per launch (replicas are independent between checks)
@@ -523,7 +538,7 @@ static gpr_status run_steps(gpr_system *S, int nrep, long long nsteps, long long
                 it.roff = k * it.nsets;
                 if (S->groups > 1) HIPCHK(S, hipMemsetAsync(S->d.sync, 0, sizeof(int) * 64 * S->R, S->stream));
                 HIPCHK(S, prof_begin(S));
-                rc = launch_persist(S, pb, nblocks, S->bt_persist, lds, coop, S->stream, true);
+                rc = launch_persist(S, pb, nblocks, S->bt_persist, lds, S->stream, true);
                 if (rc) return rc;
                 HIPCHK(S, prof_end(S));
             }
@@ -957,7 +972,7 @@ static gpr_status create_impl(const gpr_system_desc *D, gpr_system *S)
     {
         // persistent split: the fewest workgroups per replica (1, 2, 4 or 8) whose LDS fits, then
         // more while each keeps >= 256 atoms; with more than one, every workgroup of the grid
-        // must be resident at once (cooperative launch)
+        // must be resident at once (the grid is sized to what the device holds)
         int cus = 0;
         HIPCHK(S, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         S->max_coresident = cus;
@@ -1282,6 +1297,24 @@ extern "C" gpr_status gpr_profile_read(gpr_system *S, double *ms, int64_t *launc
     HIPCHK(S, prof_collect(S));
     if (ms) *ms = S->prof_ms;
     if (launches) *launches = S->prof_n;
+    return GPR_OK;
+}
+
+extern "C" gpr_status gpr_phase_read(gpr_system *S, double *out)
+{
+    if (!S || !out) return fail(S, GPR_EINVAL, "NULL argument");
+    HIPCHK(S, hipStreamSynchronize(S->stream));
+    std::vector<unsigned long long> acc((size_t)S->R * PHASE_MAX_G * NPHASE);
+    const hipError_t e = phase_take(acc.data(), S->R, S->stream);
+    if (e == hipErrorNotSupported) return fail(S, GPR_EINVAL, "library built without the phase timers");
+    HIPCHK(S, e);
+    int dev = 0, khz = 0;
+    HIPCHK(S, hipGetDevice(&dev));
+    HIPCHK(S, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    if (khz <= 0) return fail(S, GPR_EDEVICE, "no wall-clock rate");
+    const double us_per_tick = 1000.0 / (double)khz;
+    for (size_t k = 0; k < acc.size(); ++k)
+        out[k] = (k % NPHASE) < PH_NSTEP ? (double)acc[k] * us_per_tick : (double)acc[k];
     return GPR_OK;
 }
 
@@ -1714,9 +1747,8 @@ static gpr_status cycle_graph(gpr_system *S, int op, hipGraphExec_t *out)
     PersistBatch pb{};
     pb.nitems = 1;
     int nblocks = 0;
-    bool coop = false;
     const size_t lds = persist_lds(S->n, S->np, S->split);
-    gpr_status rc = persist_item(S, nrep, S->bt_persist, lds, -1, pb.it[0], nblocks, coop);
+    gpr_status rc = persist_item(S, nrep, S->bt_persist, lds, -1, pb.it[0], nblocks);
     if (rc) return rc;
     const int rounds = (nrep + pb.it[0].nsets - 1) / pb.it[0].nsets;
     rc = check_layout(S, pb, nblocks, S->bt_persist, true);
@@ -1738,21 +1770,7 @@ static gpr_status cycle_graph(gpr_system *S, int op, hipGraphExec_t *out)
                 if (e != hipSuccess) break;
             }
             void *args[] = {(void *)&it};
-            if (coop) {
-                hipLaunchAttribute attr{};
-                attr.id = hipLaunchAttributeCooperative;
-                attr.val.cooperative = 1;
-                hipLaunchConfig_t cfg{};
-                cfg.gridDim = dim3(nblocks);
-                cfg.blockDim = dim3(S->bt_persist);
-                cfg.dynamicSmemBytes = lds;
-                cfg.stream = cs;
-                cfg.attrs = &attr;
-                cfg.numAttrs = 1;
-                e = hipLaunchKernelExC(&cfg, (const void *)k_persist, args);
-            } else {
-                e = hipLaunchKernel((const void *)k_persist, dim3(nblocks), dim3(S->bt_persist), args, lds, cs);
-            }
+            e = hipLaunchKernel((const void *)k_persist, dim3(nblocks), dim3(S->bt_persist), args, lds, cs);
         }
         if (e != hipSuccess) break;
         hipLaunchKernelGGL(k_check, cgrid, dim3(256), sizeof(int) * nrep, cs, S->d_dev, dep ? CHK_DEPHASE : CHK_PARALLEL,
@@ -2053,8 +2071,7 @@ static gpr_status batch_layout(gpr_system *const *systems, int32_t nsys, const s
     std::vector<int> nb(nsys, 0);
     for (int k = 0; k < nsys; ++k) {
         if (nrep[k] <= 0) continue;
-        bool coop = false;
-        gpr_status rc = persist_item(systems[k], nrep[k], sh.bt, sh.lds, sets[k] * systems[k]->groups, items[k], nb[k], coop);
+        gpr_status rc = persist_item(systems[k], nrep[k], sh.bt, sh.lds, sets[k] * systems[k]->groups, items[k], nb[k]);
         if (rc) return rc;
     }
     slot.assign(nsys, -1);
@@ -2113,7 +2130,7 @@ extern "C" gpr_status gpr_batch_advance(gpr_system *const *systems, int32_t nsys
             it.state_end = (t[k] + kstep) % S->tcd == 0 ? 1 : 0;
             if (S->groups > 1) HIPCHK(S, hipMemsetAsync(S->d.sync, 0, sizeof(int) * 64 * S->R, stream));
         }
-        rc = launch_persist(S0, pb, nblocks, sh.bt, sh.lds, true, stream);
+        rc = launch_persist(S0, pb, nblocks, sh.bt, sh.lds, stream);
         if (rc) return rc;
         for (int k = 0; k < nsys; ++k) {
             gpr_system *S = systems[k];
@@ -2209,7 +2226,7 @@ extern "C" gpr_status gpr_batch_run(gpr_system *const *systems, int32_t nsys, gp
             it.state_end = c[k].at_check ? 1 : 0;
             if (S->groups > 1) HIPCHK(S, hipMemsetAsync(S->d.sync, 0, sizeof(int) * 64 * S->R, stream));
         }
-        rc = launch_persist(S0, pb, nblocks, sh.bt, sh.lds, true, stream);
+        rc = launch_persist(S0, pb, nblocks, sh.bt, sh.lds, stream);
         if (rc) return rc;
         for (int k = 0; k < nsys; ++k) {
             if (nrep[k] == 0) continue;

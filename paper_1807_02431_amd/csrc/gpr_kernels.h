@@ -32,6 +32,15 @@ struct CycRec {
 };
 constexpr int NO_HALT = 0x7FFFFFFF;
 
+// Phase timers of the persistent body (a build with GPR_PHASE_PROBE only): the slots of one
+// (replica, group): clock ticks spent in each phase, then the counts of steps and rebuilds.
+enum { PH_PROLOGUE = 0, PH_INTEGRATE, PH_EXCHANGE, PH_REBUILD, PH_FORCES, PH_TAIL, PH_EPILOGUE, PH_NSTEP, PH_NREBUILD,
+       NPHASE };
+constexpr int PHASE_MAX_R = 4096, PHASE_MAX_G = 8;
+// Host side: copies the slots of replicas [0, R) ([R][PHASE_MAX_G][NPHASE]) to out and clears
+// them, on the stream; hipErrorNotSupported in a build without the timers.
+hipError_t phase_take(unsigned long long *out, int R, hipStream_t st);
+
 // atom ranges of the workgroups of one replica on the persistent path
 struct Split {
     int G;          // workgroups per replica (1, 2, 4 or 8)

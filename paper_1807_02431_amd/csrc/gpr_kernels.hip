@@ -1075,6 +1075,46 @@ __global__ void __launch_bounds__(256) k_unfix_out(const Dev *__restrict__ Sp, d
 }
 
 // ================================================================== persistent path
+// Phase timers, in a build with GPR_PHASE_PROBE defined (a measurement library built beside
+// the product one; the product build has none of this).  Thread 0 of every workgroup reads
+// the constant-rate clock at the ends of the phases of each step and adds the differences,
+// per (replica, group), to gpr_phase_acc[(r * PHASE_MAX_G + g) * NPHASE + k]; the phases end
+// at workgroup barriers the body has anyway, so thread 0's clock marks the group's progress.
+// The timers add a few instructions per phase and change no result.
+#ifdef GPR_PHASE_PROBE
+__device__ unsigned long long gpr_phase_acc[PHASE_MAX_R * PHASE_MAX_G * NPHASE];
+// (the last reading is kept in LDS too, so that no register is held across the phases)
+#define PHASE_MARK(k)                                                       \
+    do {                                                                    \
+        if (tid == 0) {                                                     \
+            const unsigned long long t_ = __builtin_amdgcn_s_memrealtime(); \
+            ph_acc[(k)] += t_ - ph_acc[NPHASE];                             \
+            ph_acc[NPHASE] = t_;                                            \
+        }                                                                   \
+    } while (0)
+#define PHASE_COUNT(k) do { if (tid == 0) ph_acc[(k)] += 1; } while (0)
+#else
+#define PHASE_MARK(k) ((void)0)
+#define PHASE_COUNT(k) ((void)0)
+#endif
+
+hipError_t phase_take(unsigned long long *out, int R, hipStream_t st)
+{
+#ifdef GPR_PHASE_PROBE
+    if (R < 1 || R > PHASE_MAX_R) return hipErrorInvalidValue;
+    const size_t bytes = sizeof(unsigned long long) * (size_t)R * PHASE_MAX_G * NPHASE;
+    void *acc = nullptr;
+    hipError_t e = hipGetSymbolAddress(&acc, HIP_SYMBOL(gpr_phase_acc));
+    if (e == hipSuccess) e = hipMemcpyAsync(out, acc, bytes, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemsetAsync(acc, 0, bytes, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return e;
+#else
+    (void)out; (void)R; (void)st;
+    return hipErrorNotSupported;
+#endif
+}
+
 // Barrier among the G workgroups of one replica: every thread waits for its own global
 // stores to complete, then one thread adds to the replica's counter (device-scope relaxed
 // atomic) and waits, with a bounded spin, for all G arrivals of this generation.  Data
@@ -1179,6 +1219,10 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
     __shared__ int sbuf, bbuf, hbuf, hist[64], ptask;
 
     const int tid = threadIdx.x, BT = blockDim.x;
+#ifdef GPR_PHASE_PROBE
+    __shared__ unsigned long long ph_acc[NPHASE + 1];
+    if (tid < NPHASE) ph_acc[tid] = 0;
+#endif
     const size_t b = (size_t)r * 3 * np;
     GPR_GLOBAL float *xg = gmut(S.x) + b, *xbg = gmut(S.xb) + b;
     float *vg = S.v + b;
@@ -1192,6 +1236,9 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
     float *xch_z0 = S.xchg + 2 * b + 4 * np;                                        // [2][np] z
     int gen = 0;
 
+#ifdef GPR_PHASE_PROBE
+    if (tid == 0) ph_acc[NPHASE] = __builtin_amdgcn_s_memrealtime();
+#endif
     stage_replica(S, r, xs, pp, tid, BT);
     for (int k = tid; k < 3 * lmax; k += BT) {
         const int d = k / lmax, a = a0 + k % lmax;
@@ -1241,6 +1288,7 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
     long long *eacc = red + MAX_OBS * 8;
     bool alive = true;
     bool pend = false;                                      // the previous step's closing B is due
+    PHASE_MARK(PH_PROLOGUE);
 
     for (int step = 0; step < nsteps && alive; ++step) {
         const long long s = s0 + step;
@@ -1284,6 +1332,7 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
                 // fetch the other groups' positions
                 asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
                 __syncthreads();                     // own positions stored, forces read
+                PHASE_MARK(PH_INTEGRATE);
                 if (tid == 0) {
                     __hip_atomic_fetch_add(sync, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     bbuf = 1;
@@ -1340,10 +1389,13 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
             any_hit = hbuf;
         } else {
             any_hit = __syncthreads_or(hit);
+            PHASE_MARK(PH_INTEGRATE);
         }
+        PHASE_MARK(PH_EXCHANGE);
         // each replica is its own set of workgroups here, so its list is rebuilt when it is
         // period steps old (or flagged), independently of the other replicas
         if (need || (cutoff_on && (any_hit || s - lastb >= period))) {
+            PHASE_COUNT(PH_NREBUILD);
             lastb = s;
             block_spheres(S, xs, sph, tid, BT);
             __syncthreads();
@@ -1364,6 +1416,7 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
             if (need && g == 0 && tid == 0) S.list_pad[r] = 1;
             need = false;
         }
+        PHASE_MARK(PH_REBUILD);
         if (!split) {
             for (int k = tid; k < 3 * lmax; k += BT) fa[k] = 0;
             if (tid == 0) { *eacc = 0; ptask = 0; }
@@ -1414,6 +1467,7 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
             }
         }
         __syncthreads();
+        PHASE_MARK(PH_FORCES);
         // the closing B: here when the step's velocities are read (a sample, the end of the
         // launch), else by the next step's integrator
         pend = !(samp || step + 1 == nsteps);
@@ -1458,6 +1512,8 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
             }
         }
         __syncthreads();
+        PHASE_MARK(PH_TAIL);
+        PHASE_COUNT(PH_NSTEP);
     }
     // write back this group's atoms
     for (int a = a0 + tid; a < a1; a += BT) {
@@ -1478,6 +1534,11 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
         const int id = state_wg(S, xs, red, &sbuf, tid, BT);
         if (tid == 0) S.state[r] = id;
     }
+#ifdef GPR_PHASE_PROBE
+    PHASE_MARK(PH_EPILOGUE);
+    if (tid == 0 && r < PHASE_MAX_R && g < PHASE_MAX_G)
+        for (int k = 0; k < NPHASE; ++k) gpr_phase_acc[((size_t)r * PHASE_MAX_G + g) * NPHASE + k] += ph_acc[k];
+#endif
 }
 
 // One system, one replica per set: replicas roff, roff + 1, ... (a system with more replicas

@@ -12,6 +12,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgpr_hip.so")
+PROBE_LIB_PATH = os.path.join(_HERE, "libgpr_hip_probe.so")   # the same sources with phase timers
+PHASES = ("prologue", "integrate", "exchange", "rebuild", "forces", "tail", "epilogue")
 
 OK, BUDGET = 0, 1
 EINVAL, ENOMEM, EDEVICE, EPHASE, EUNSTABLE = -1, -2, -3, -4, -5
@@ -109,6 +111,7 @@ SIGNATURES = {
     "gpr_get_accumulators": (C.c_int32, [_VP, _P64, _PD, _PD, _PD]),
     "gpr_profile": (C.c_int32, [_VP, C.c_int32]),
     "gpr_profile_read": (C.c_int32, [_VP, _PD, _P64]),
+    "gpr_phase_read": (C.c_int32, [_VP, _PD]),
     "gpr_observe": (C.c_int32, [_VP, _PD, _PI]),
     "gpr_philox_noise": (C.c_int32, [C.c_uint64, C.c_int32, C.c_int64, C.c_int32, C.c_int32,
                                      C.POINTER(C.c_uint32), C.POINTER(C.c_float)]),
@@ -152,6 +155,17 @@ def lib():
             f.argtypes = args
         _lib = L
     return _lib
+
+
+def use_probe_library():
+    """Load the phase-timer build (libgpr_hip_probe.so) instead of the product library, for
+    measurement; must come before the first call into the library."""
+    global LIB_PATH
+    if _lib is not None:
+        raise RuntimeError("the library is already loaded")
+    if not os.path.exists(PROBE_LIB_PATH):
+        raise ImportError("libgpr_hip_probe.so is not built (run paper_1807_02431_amd/build.py --probe)")
+    LIB_PATH = PROBE_LIB_PATH
 
 
 def _d(a):
@@ -305,6 +319,14 @@ class System:
         n = C.c_int64()
         self._c(lib().gpr_profile_read(self._h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def phase_read(self):
+        """gpr_phase_read (timer build only): [R, 8, 9] per replica and workgroup, the
+        microseconds in each of PHASES, then the counts of steps and of pair-list rebuilds,
+        since the last read."""
+        out = np.zeros((self.R, 8, 9))
+        self._c(lib().gpr_phase_read(self._h, out.ctypes.data_as(_PD)))
+        return out
 
     # -------------------------------------------------------------- queries
     def energy_forces(self, r0=0, nr=None):

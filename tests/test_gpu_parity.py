@@ -3,7 +3,8 @@
 Bars: bit-exact for integer and index work (Philox words, Fleming-Viot plans, exit votes)
 and for the FP64 Gelman-Rubin reduction on identical inputs; forces within 1e-5 of the
 largest force component (per replica) at identical positions; positions within 1e-5 of the
-largest coordinate after 100 BAOAB steps under identical Philox streams; the two stepping
+largest coordinate after 100 BAOAB steps under identical Philox streams, velocities within
+the bar that this implies through the stiffest harmonic term (_vel_bar); the two stepping
 paths bit-identical to each other; exit statistics by a two-sample KS test (p > 0.05)."""
 import sys
 
@@ -117,6 +118,24 @@ def _pos_err(qg, qo):
     return np.abs(qg - qo).max() / np.abs(qo).max()
 
 
+def _vel_bar(spec, qo):
+    """The velocity bar that the position bar implies.  The fastest motion is the stiffest
+    harmonic term (bond: omega = sqrt(k / mu), mu the reduced mass; restraint: sqrt(k / m)),
+    and a position error dx on it appears in the velocity as about omega * dx; with dx at the
+    position bar, 1e-5 of the largest coordinate: |dv| <= omega_max * 1e-5 * max|x|."""
+    m = np.asarray(spec["mass"], np.float64)
+    b = np.asarray(spec["bonds"]).reshape(-1, 2)
+    om = 0.0
+    if len(b):
+        mu = m[b[:, 0]] * m[b[:, 1]] / (m[b[:, 0]] + m[b[:, 1]])
+        om = np.sqrt(np.asarray(spec["bond_k"], np.float64) / mu).max()
+    ri = np.asarray(spec.get("restraints", []), np.int64)
+    if len(ri):
+        om = max(om, np.sqrt(np.asarray(spec["restraint_k"], np.float64) / m[ri]).max())
+    assert om > 0
+    return om * 1e-5 * np.abs(qo).max()
+
+
 @pytest.mark.parametrize("path", [0, 1])
 @pytest.mark.parametrize("name", ["chain22", "rl300"])
 def test_positions_100_steps_small(name, path):
@@ -133,7 +152,7 @@ def test_positions_100_steps_small(name, path):
         qo, vo = o.get_state(r)
         err = _pos_err(qg, qo)
         assert err < 1e-5, (r, err)
-        assert np.abs(vg - vo).max() < 1e-3 * np.abs(vo).max()
+        assert np.abs(vg - vo).max() < _vel_bar(spec, qo), (r, np.abs(vg - vo).max(), _vel_bar(spec, qo))
 
 
 @pytest.mark.parametrize("path", [0, 1])
@@ -146,11 +165,13 @@ def test_positions_100_steps_full_size_sampled(path):
     for r in (0, 37, 63):
         o = oracle.System(spec)
         o.step_replicas(100, r, r + 1)
-        qg, _ = g.get_state(r)
-        qo, _ = o.get_state(r)
+        qg, vg = g.get_state(r)
+        qo, vo = o.get_state(r)
         err = _pos_err(qg, qo)
-        say("replica", r, "pos rel err", err)
+        dv = np.abs(vg - vo).max()
+        say("replica", r, "pos rel err", err, "vel err", dv, "bar", _vel_bar(spec, qo))
         assert err < 1e-5
+        assert dv < _vel_bar(spec, qo)
 
 
 def test_plain_and_persistent_paths_bit_identical():
