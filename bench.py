@@ -427,7 +427,7 @@ def phases_bench(lengths=(1000, 20), launches=(3, 50), warmup=300):
             s.advance(L, first_exit=False)
         kms, kn = s.profile_read()
         s.profile(False)
-        ph = s.phase_read()                                   # [R, 8, 9]
+        ph = s.phase_read()                                   # [R, 8, 11]
         live = ph[:, :, 7] > 0                                 # (replica, group) slots that ran
         steps = ph[:, :, 7][live].mean()
         kn = max(kn, 1)                                        # kernel launches (a call that
@@ -439,6 +439,14 @@ def phases_bench(lengths=(1000, 20), launches=(3, 50), warmup=300):
             else:
                 per[name + "_us_per_step"] = float(v.mean() / steps)
         tot = ph[:, :, :7].sum(axis=2)[live]
+        # the work a group does between two exchanges (all but the exchange wait), per step:
+        # how far the busiest group of a replica is ahead of the replica's mean
+        G = int(live[0].sum())
+        own = (ph[:, :G, :7].sum(axis=2) - ph[:, :G, 2]) / steps
+        per["group_imbalance_us_per_step"] = float((own.max(axis=1) - own.mean(axis=1)).mean())
+        # the last launch: how far apart its workgroups started, and when the last one ended
+        per["last_launch_start_spread_us"] = float(ph[:, :, 9][live].max())
+        per["last_launch_span_us"] = float(ph[:, :, 10][live].max())
         out["calls_of_%d_steps" % L] = dict(
             calls=nl, kernel_launches=kn, steps_per_group=float(steps),
             rebuilds_per_step=float(ph[:, :, 8][live].mean() / steps),

@@ -411,13 +411,15 @@ gpr_status gpr_profile_read(gpr_system *sys, double *ms, int64_t *launches);
 
 /* Phase timers of the persistent kernel, for measurement: only the library's timer build
  * (libgpr_hip_probe.so, the same sources built with GPR_PHASE_PROBE) records them; the
- * product build returns GPR_EINVAL.  out ([R][8][9] doubles, host, caller-owned) receives per
- * replica r and workgroup g of its replica (rows g >= G stay 0) the microseconds spent since
+ * product build returns GPR_EINVAL.  out ([R][8][11] doubles, host, caller-owned) receives per
+ * replica r and workgroup g of its replica (rows g >= G stay 0): the microseconds spent since
  * the last read in the launch prologue (staging), the integrator (B A O A and the position
- * stores), the exchange (barrier and the other groups' positions), the pair-list rebuild, the
- * forces (bonded and pair terms), the step's tail (closing B, samples) and the epilogue (write
- * back), then the number of steps and of pair-list rebuilds; the totals are then cleared.
- * Waits for the system's stream.  Several systems advanced together share the totals. */
+ * stores), the exchange (the other groups' positions), the pair-list rebuild, the forces
+ * (bonded and pair terms), the step's tail (closing B, samples) and the epilogue (write back);
+ * the number of steps and of pair-list rebuilds; then the start and the end of the group's
+ * last launch, in microseconds after the earliest start among all groups.  The totals are
+ * then cleared.  Waits for the system's stream.  Several systems advanced together share the
+ * totals. */
 gpr_status gpr_phase_read(gpr_system *sys, double *out);
 
 /* Observable accumulators of replicas [0, R): n (samples) and, per replica r and observable

@@ -1313,8 +1313,15 @@ extern "C" gpr_status gpr_phase_read(gpr_system *S, double *out)
     HIPCHK(S, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
     if (khz <= 0) return fail(S, GPR_EDEVICE, "no wall-clock rate");
     const double us_per_tick = 1000.0 / (double)khz;
-    for (size_t k = 0; k < acc.size(); ++k)
-        out[k] = (k % NPHASE) < PH_NSTEP ? (double)acc[k] * us_per_tick : (double)acc[k];
+    unsigned long long t0 = ~0ull;                        // the earliest start of the last launches
+    for (size_t k = PH_START; k < acc.size(); k += NPHASE)
+        if (acc[k]) t0 = std::min(t0, acc[k]);
+    for (size_t k = 0; k < acc.size(); ++k) {
+        const size_t slot = k % NPHASE;
+        if (slot < PH_NSTEP) out[k] = (double)acc[k] * us_per_tick;
+        else if (slot < PH_START) out[k] = (double)acc[k];
+        else out[k] = acc[k] ? (double)(acc[k] - t0) * us_per_tick : 0.0;
+    }
     return GPR_OK;
 }
 

@@ -33,9 +33,10 @@ struct CycRec {
 constexpr int NO_HALT = 0x7FFFFFFF;
 
 // Phase timers of the persistent body (a build with GPR_PHASE_PROBE only): the slots of one
-// (replica, group): clock ticks spent in each phase, then the counts of steps and rebuilds.
+// (replica, group): clock ticks spent in each phase, the counts of steps and rebuilds (all
+// summed over launches), then the clock at the start and at the end of its last launch.
 enum { PH_PROLOGUE = 0, PH_INTEGRATE, PH_EXCHANGE, PH_REBUILD, PH_FORCES, PH_TAIL, PH_EPILOGUE, PH_NSTEP, PH_NREBUILD,
-       NPHASE };
+       PH_START, PH_END, NPHASE };
 constexpr int PHASE_MAX_R = 4096, PHASE_MAX_G = 8;
 // Host side: copies the slots of replicas [0, R) ([R][PHASE_MAX_G][NPHASE]) to out and clears
 // them, on the stream; hipErrorNotSupported in a build without the timers.

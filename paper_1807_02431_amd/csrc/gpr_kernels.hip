@@ -1237,7 +1237,7 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
     int gen = 0;
 
 #ifdef GPR_PHASE_PROBE
-    if (tid == 0) ph_acc[NPHASE] = __builtin_amdgcn_s_memrealtime();
+    if (tid == 0) ph_acc[NPHASE] = ph_acc[PH_START] = __builtin_amdgcn_s_memrealtime();
 #endif
     stage_replica(S, r, xs, pp, tid, BT);
     for (int k = tid; k < 3 * lmax; k += BT) {
@@ -1536,8 +1536,12 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
     }
 #ifdef GPR_PHASE_PROBE
     PHASE_MARK(PH_EPILOGUE);
-    if (tid == 0 && r < PHASE_MAX_R && g < PHASE_MAX_G)
-        for (int k = 0; k < NPHASE; ++k) gpr_phase_acc[((size_t)r * PHASE_MAX_G + g) * NPHASE + k] += ph_acc[k];
+    if (tid == 0 && r < PHASE_MAX_R && g < PHASE_MAX_G) {
+        unsigned long long *acc = gpr_phase_acc + ((size_t)r * PHASE_MAX_G + g) * NPHASE;
+        for (int k = 0; k < PH_START; ++k) acc[k] += ph_acc[k];
+        acc[PH_START] = ph_acc[PH_START];
+        acc[PH_END] = __builtin_amdgcn_s_memrealtime();
+    }
 #endif
 }
 

@@ -321,10 +321,10 @@ class System:
         return ms.value, n.value
 
     def phase_read(self):
-        """gpr_phase_read (timer build only): [R, 8, 9] per replica and workgroup, the
-        microseconds in each of PHASES, then the counts of steps and of pair-list rebuilds,
-        since the last read."""
-        out = np.zeros((self.R, 8, 9))
+        """gpr_phase_read (timer build only): [R, 8, 11] per replica and workgroup, the
+        microseconds in each of PHASES and the counts of steps and of pair-list rebuilds since
+        the last read, then the start and end of the last launch (µs after its earliest start)."""
+        out = np.zeros((self.R, 8, 11))
         self._c(lib().gpr_phase_read(self._h, out.ctypes.data_as(_PD)))
         return out
 

@@ -110,7 +110,7 @@ def test_check_cycles_match_host_checks(name, groups, cycles):
     """Convergence and parallel steps as replays of captured check cycles (gpr_set_cycles): the
     loop of Fig. 1 gives the same events, clock, branch and sample counts, R-hat bits and
     configurations as with one host round trip per check; with two workgroups per replica the
-    captured persistent launches are cooperative."""
+    captured persistent launches synchronise the groups of a replica across CUs."""
     gpr = _gpr()
     if name == "toy":
         spec = dict(G.toy2d(n_replicas=64, seed=9), pos=np.array([[-0.2], [0.0], [0.0]]))

@@ -60,8 +60,8 @@ def test_probe_build_same_results_and_timers_add_up(tmp_path):
     info = json.loads(p.stdout.strip().splitlines()[-1])
     got = np.load(out)
     assert np.array_equal(got, ref)
-    ph = np.load(phf)                                   # [R, 8, 9]
-    assert ph.shape == (8, 8, 9)
+    ph = np.load(phf)                                   # [R, 8, 11]
+    assert ph.shape == (8, 8, 11)
     assert np.all(ph[:, :2, 7] == 120) and np.all(ph[:, 2:, :] == 0)
     assert np.all(ph[:, :2, 8] >= 1)                    # the list is built at least once
     assert np.all(ph[:, :2, :7] >= 0)
@@ -71,3 +71,7 @@ def test_probe_build_same_results_and_timers_add_up(tmp_path):
     # a group's phases lie inside its launches, and the slowest group fills most of them
     assert tot.max() <= kernel_us * 1.02 + 5.0, (tot.max(), kernel_us)
     assert tot.max() >= 0.5 * kernel_us, (tot.max(), kernel_us)
+    # the last launch's start and end (µs after its earliest start) bound a 60-step launch
+    st, en = ph[:, :2, 9], ph[:, :2, 10]
+    assert st.min() == 0.0 and np.all(en > st)
+    assert en.max() <= kernel_us, (en.max(), kernel_us)
