@@ -1216,7 +1216,7 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
     int *wscr = (int *)(sph + (n + BLK - 1) / BLK);        // [16][WBLK] build scratch per wave
     unsigned short *perm = (unsigned short *)(wscr + 16 * WBLK);   // [16 ceil(lmax / 16)] pair-loop order
     unsigned short *keyl = perm + 16 * ((lmax + 15) >> 4);  // [lmax] groups in each of an atom's sub-lists
-    __shared__ int sbuf, bbuf, hbuf, hist[64], ptask;
+    __shared__ int sbuf, bbuf, hbuf, hist[64], ptask, btask;
 
     const int tid = threadIdx.x, BT = blockDim.x;
 #ifdef GPR_PHASE_PROBE
@@ -1397,11 +1397,35 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
         if (need || (cutoff_on && (any_hit || s - lastb >= period))) {
             PHASE_COUNT(PH_NREBUILD);
             lastb = s;
+            // The search in tasks of 16 consecutive atoms (one wave each), costliest first by
+            // the lists of the last build (the summed longest sub-lists of the task's atoms),
+            // taken by the waves from a counter as they come free.  The order changes no list:
+            // each lane builds its own sub-list.  The costs sit in the waves' search scratch
+            // until the search starts (16 WBLK ints hold the tasks of 16,384 atoms).
+            const int ntk = (nl + 15) >> 4;
+            int *tcost = wscr;
+            for (int c = tid; c < ntk; c += BT) {
+                int sum = 0;
+                for (int l = 16 * c; l < min(16 * c + 16, nl); ++l) sum += keyl[l];
+                tcost[c] = sum;
+            }
+            if (tid == 0) btask = 0;
             block_spheres(S, xs, sph, tid, BT);
             __syncthreads();
-            for (int L0 = a0 * P; L0 < a1 * P; L0 += BT) {
-                if (L0 + (tid & ~63) >= a1 * P) continue;          // whole wave past the group's atoms
-                const int L = L0 + tid, i = L / P, q = L % P;
+            for (int c = tid; c < ntk; c += BT) {
+                const int mine = tcost[c];
+                int rank = 0;
+                for (int d = 0; d < ntk; ++d) rank += (tcost[d] > mine) | (tcost[d] == mine && d < c);
+                perm[rank] = (unsigned short)c;
+            }
+            __syncthreads();
+            for (;;) {
+                int t = 0;
+                if ((tid & 63) == 0) t = atomicAdd(&btask, 1);
+                t = __builtin_amdgcn_readfirstlane(__shfl(t, 0, 64));
+                if (t >= ntk) break;
+                const int c = __builtin_amdgcn_readfirstlane((int)perm[t]);
+                const int L = a0 * P + 64 * c + (tid & 63), i = L / P, q = L % P;
                 const bool valid = L < a1 * P;
                 const int ngw = build_wave<4, true>(S, r, i, q, valid, (const GPR_LDS gv_f4 *)xs,
                                               (const GPR_LDS gv_f4 *)sph, (GPR_LDS int *)wscr + (tid >> 6) * WBLK,
@@ -1412,6 +1436,7 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
                     keyl[l] = (unsigned short)ngw;
                 }
             }
+            __syncthreads();                     // every task has read its entry of perm
             order_atoms(keyl, perm, hist, nl, tid, BT);
             if (need && g == 0 && tid == 0) S.list_pad[r] = 1;
             need = false;
