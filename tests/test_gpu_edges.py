@@ -216,3 +216,35 @@ def test_far_exclusions_match_oracle(path):
         qg, _ = g.get_state(r)
         qo, _ = o.get_state(r)
         assert np.abs(qg - qo).max() < 1e-5 * np.abs(qo).max()
+
+
+@pytest.mark.parametrize("path", [0, 1])
+def test_advance_without_first_exit_readback(path):
+    """gpr_advance with first_exit_check = NULL records and reads back nothing of the checks
+    and takes the same steps: after calls without the readback, a call with it reports the
+    first exit checks of its own steps only (counted over all calls), as on a handle that read
+    them back all along.  The 300-atom system's state is split near its start so that
+    replicas leave it within a few checks (t_check = 20)."""
+    gpr = _gpr()
+    rl = G.config("rl300", n_replicas=8, t_check=20)
+    L = rl["n_atoms"] - 32 + 10
+    dih = [L, L + 1, L + 2, L + 3]
+    o = oracle.System(dict(rl, n_replicas=2, obs=[dict(kind=G.OBS_DIHEDRAL, atoms=dih)]))
+    phi0 = o.observables_of(rl["pos"], np.zeros((3, rl["n_atoms"])), 0.0)[0]
+    rl["state"] = dict(kind=G.STATE_DIHEDRAL_BOXES, atoms=dih + dih,
+                       boxes=[[-4.0, phi0 + 0.02, -4.0, 4.0], [phi0 + 0.02, 4.0, -4.0, 4.0]])
+    a = gpr.System(rl, path=path)
+    b = gpr.System(rl, path=path)
+    say("advance without readback, path", path)
+    fa = [a.advance(30) for _ in range(3)]
+    for _ in range(3):
+        assert b.advance(30, first_exit=False) is None
+    assert a.advance_steps() == b.advance_steps() == 90
+    for r in range(8):
+        assert np.array_equal(a.get_state(r)[0], b.get_state(r)[0])
+        assert np.array_equal(a.get_state(r)[1], b.get_state(r)[1])
+    ga, gb = a.advance(60), b.advance(60)
+    assert np.array_equal(ga, gb)
+    # checks at steps 100, 120, 140 of the schedule: indices 5, 6, 7
+    assert all(v == 0 or 5 <= v <= 7 for v in gb), gb
+    assert any(np.any(f > 0) for f in fa + [ga]), "no replica left the state; the split is too far"
