@@ -489,12 +489,16 @@ __device__ __forceinline__ float4 nb_lane_t(const NbConsts &S, int r, int i, int
     const float2 ppi = pp[i];
     const float rc2 = S.rc2, krf = S.krf, krf2 = 2.0f * S.krf, crf = S.crf;
     float fx = 0.f, fy = 0.f, fz = 0.f, e = 0.f;
-    // the next word is read one group ahead, without a branch (the last group re-reads itself)
+    // the next word is read one group ahead, without a branch, through a running pointer that
+    // stops at the last group (which is then read again, from the cache)
+    const GPR_GLOBAL uint2 *Ln = L;
+    const unsigned step = (unsigned)stride;
     uint2 nxt = make_uint2(0u, 0u);
-    if (ng > 0) nxt = gld(L);
+    if (ng > 0) nxt = gld(Ln);
     for (int g = 0; g < ng; ++g) {
         const uint2 cur = nxt;
-        nxt = gld(L + (size_t)min(g + 1, ng - 1) * stride);
+        Ln += g + 1 < ng ? step : 0u;
+        nxt = gld(Ln);
         const int j0 = cur.x & 0xFFFF, j1 = cur.x >> 16, j2 = cur.y & 0xFFFF, j3 = cur.y >> 16;
         const float4 x0 = xs[j0], x1 = xs[j1], x2 = xs[j2], x3 = xs[j3];
         const float2 p0 = pp[j0], p1 = pp[j1], p2 = pp[j2], p3 = pp[j3];
