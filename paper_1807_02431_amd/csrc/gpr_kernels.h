@@ -81,7 +81,9 @@ struct PersistBatch {
 // Work items of persistent launches: an item is a system whose replicas are shared by nsets
 // sets of sp.G workgroups.  Workgroup `local` of the item (counted from boff) is group g of set
 // `set`.  With xcd set (nsets a multiple of 8) the workgroups of a set have equal blockIdx mod
-// 8, i.e. sit on one XCD and share its L2.  Host code checks every launch's layout with it.
+// 8, which under the round-robin dispatch of workgroups to XCDs puts them on one XCD, for L2
+// locality only: what they exchange is device-coherent.  Host code checks every launch's
+// layout with it.
 __host__ __device__ inline bool persist_place(const PersistItem &it, int local, int &set, int &g)
 {
     const int G = it.sp.G;

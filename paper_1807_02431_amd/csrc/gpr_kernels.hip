@@ -1170,8 +1170,9 @@ __device__ __forceinline__ float2 ld_coh2(const unsigned long long *p)
 // own atoms when due -> bonded terms touching own atoms (LDS atomics) -> pair forces of own
 // atoms (P lanes per atom) -> closing B; every t_GR steps (t counted from t0) the observables
 // of workers are accumulated by group 0.  With state_end group 0 writes the state id.
-// Workgroups map to replicas so that a replica's groups share an XCD (blockIdx mod 8) when the
-// replica count allows; results do not depend on G or the block size.
+// Workgroups map to replicas so that a replica's groups are meant to share an XCD (equal
+// blockIdx mod 8) when the replica count allows; results do not depend on G, the block size or
+// the placement.
 // Pair-loop order of a group's nl atoms.  A task of the pair loop is 16 atoms on the 64 lanes
 // of a wave and runs as long as its longest list, so the atoms go longest list first (key: the
 // atom's longest sub-list, in words): tasks of similar lists, taken heaviest first.  perm has
