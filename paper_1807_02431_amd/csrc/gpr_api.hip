@@ -173,17 +173,29 @@ long long count_samples(long long t_old, long long t_new, int t_gr) { return t_n
 static void drop_cycle_graphs(gpr_system *S);
 
 // event pair around the next timed launch (created on first use, reused afterwards)
+// one more pair of timing events (created ahead by gpr_profile, so that a timed call does not
+// create them; more only when a call launches the kernel more often than that)
+static hipError_t prof_add_pair(gpr_system *S)
+{
+    hipEvent_t a, b;
+    hipError_t e = hipEventCreate(&a);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&b);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return e;
+    }
+    S->ev_a.push_back(a);
+    S->ev_b.push_back(b);
+    return hipSuccess;
+}
+
 static hipError_t prof_begin(gpr_system *S)
 {
     if (!S->prof) return hipSuccess;
     if (S->ev_used == S->ev_a.size()) {
-        hipEvent_t a, b;
-        hipError_t e = hipEventCreate(&a);
+        const hipError_t e = prof_add_pair(S);
         if (e != hipSuccess) return e;
-        e = hipEventCreate(&b);
-        if (e != hipSuccess) return e;
-        S->ev_a.push_back(a);
-        S->ev_b.push_back(b);
     }
     return hipEventRecord(S->ev_a[S->ev_used], S->stream);
 }
@@ -1287,6 +1299,7 @@ extern "C" gpr_status gpr_profile(gpr_system *S, int32_t enable)
     S->prof = enable != 0;
     S->prof_ms = 0.0;
     S->prof_n = 0;
+    while (S->prof && S->ev_a.size() < 8) HIPCHK(S, prof_add_pair(S));
     return GPR_OK;
 }
 
