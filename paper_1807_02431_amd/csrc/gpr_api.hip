@@ -548,7 +548,6 @@ static gpr_status run_steps(gpr_system *S, int nrep, long long nsteps, long long
             it.state_end = (state_end && last) ? 1 : 0;
             for (int k = 0; k < rounds; ++k) {
                 it.roff = k * it.nsets;
-                if (S->groups > 1) HIPCHK(S, hipMemsetAsync(S->d.sync, 0, sizeof(int) * 64 * S->R, S->stream));
                 HIPCHK(S, prof_begin(S));
                 rc = launch_persist(S, pb, nblocks, S->bt_persist, lds, S->stream, true);
                 if (rc) return rc;
@@ -1784,11 +1783,6 @@ static gpr_status cycle_graph(gpr_system *S, int op, hipGraphExec_t *out)
         it.cycle = j;
         for (int k = 0; k < rounds && e == hipSuccess; ++k) {
             it.roff = k * it.nsets;
-            if (S->groups > 1) {
-                hipLaunchKernelGGL(k_zero_ints, dim3((64 * nrep + 255) / 256), dim3(256), 0, cs, S->d.sync, 64 * nrep);
-                e = hipGetLastError();
-                if (e != hipSuccess) break;
-            }
             void *args[] = {(void *)&it};
             e = hipLaunchKernel((const void *)k_persist, dim3(nblocks), dim3(S->bt_persist), args, lds, cs);
         }
@@ -2148,7 +2142,6 @@ extern "C" gpr_status gpr_batch_advance(gpr_system *const *systems, int32_t nsys
             it.t0 = (int)(t[k] % S->t_gr);
             it.sample = 1;
             it.state_end = (t[k] + kstep) % S->tcd == 0 ? 1 : 0;
-            if (S->groups > 1) HIPCHK(S, hipMemsetAsync(S->d.sync, 0, sizeof(int) * 64 * S->R, stream));
         }
         rc = launch_persist(S0, pb, nblocks, sh.bt, sh.lds, stream);
         if (rc) return rc;
@@ -2244,7 +2237,6 @@ extern "C" gpr_status gpr_batch_run(gpr_system *const *systems, int32_t nsys, gp
             it.t0 = (int)(c[k].t0 % S->t_gr);
             it.sample = c[k].sample ? 1 : 0;
             it.state_end = c[k].at_check ? 1 : 0;
-            if (S->groups > 1) HIPCHK(S, hipMemsetAsync(S->d.sync, 0, sizeof(int) * 64 * S->R, stream));
         }
         rc = launch_persist(S0, pb, nblocks, sh.bt, sh.lds, stream);
         if (rc) return rc;

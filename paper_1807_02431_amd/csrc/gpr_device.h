@@ -96,7 +96,7 @@ struct Dev {
     long long *last_build;                 // [2][R] step of the last pair-list build, by step parity
     long long *clock;                      // [2]: global step s and steps t of the current call (device-clocked plain steps)
     int *err;                              // [4] error flags
-    int *sync;                             // [R][64] per-replica barrier counter and flags (groups > 1)
+    int *sync;                             // [R][64] per-replica barrier counter, flags, leave count (groups > 1)
     float *xchg;                           // [R][2][3][np] position exchange between a replica's groups (by step parity)
     long long *esum;                       // [R] energy partial sums of a replica's groups
     double *acc;                           // [R][MAX_OBS][2]

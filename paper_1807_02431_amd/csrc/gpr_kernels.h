@@ -110,7 +110,6 @@ __global__ void k_weighted_dx(const Dev *__restrict__ Sp, const double *w, float
 __global__ void k_check(const Dev *__restrict__ Sp, int mode, long long s, int omega, int nrep, long long nsamp,
                         long long check_index, long long t_check, Status *st, int *donor, int *surv, long long *fec,
                         CycRec *cyc, int cycle);
-__global__ void k_zero_ints(int *p, int n);
 __global__ void k_clone(const Dev *__restrict__ Sp, const int *donor, int acc_mode);
 __global__ void k_init_vel(const Dev *__restrict__ Sp, float kT);
 __global__ void k_noise_test(uint32_t k0, uint32_t k1, int replica, long long step, int stream, int n,

@@ -1564,6 +1564,17 @@ __device__ __forceinline__ void persist_replica(const Dev &S, int G, int lmax, i
         const int id = state_wg(S, xs, red, &sbuf, tid, BT);
         if (tid == 0) S.state[r] = id;
     }
+    if (G > 1 && nsteps > 0) {
+        // the replica's barrier line is left clear for the next launch by the last of its groups
+        // to finish (each group counts itself out in slot 8 once none of its waves reads the
+        // line again), so that no launch needs it cleared beforehand
+        __syncthreads();
+        if (tid == 0 && __hip_atomic_fetch_add(sync + 8, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == G - 1) {
+            __hip_atomic_store(sync, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int k = 16; k < 64; k += 16) __hip_atomic_store(sync + k, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(sync + 8, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
 #ifdef GPR_PHASE_PROBE
     PHASE_MARK(PH_EPILOGUE);
     if (tid == 0 && r < PHASE_MAX_R && g < PHASE_MAX_G) {
@@ -1592,11 +1603,6 @@ __global__ void __launch_bounds__(1024) k_persist(PersistItem it)
     }
     persist_replica(*it.dev, it.sp.G, it.sp.lmax, it.sp.bnd[g], it.sp.bnd[g + 1], set + it.roff, g, s0, it.nsteps,
                     t0, it.sample, it.state_end);
-}
-
-__global__ void __launch_bounds__(256) k_zero_ints(int *p, int n)
-{
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) p[k] = 0;
 }
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
