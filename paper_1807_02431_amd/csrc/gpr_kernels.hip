@@ -241,18 +241,19 @@ __device__ __forceinline__ float wave16_max(float v)
 
 // Pair lists of the 16 atoms of one wave; lane = 4 (i - i0) + q for the wave's first atom
 // i0.  All 64 lanes call it together: the culling is wave-wide (each lane tests a block
-// sphere against the bounding sphere of the wave's atoms, and the wave visits the blocks that
+// sphere against the bounding box of the wave's atoms, and the wave visits the blocks that
 // any lane found near); lanes with valid == false take part but own no list.
 // Sub-list (i, q): partners j = q (mod P), j != i, not excluded, |x_i - x_j| < r_list, in
 // ascending order; entry k is the 16-bit word k % 4 of group k / 4; the last group is padded
 // with the dummy atom n.  allpairs: no distance tests (vacuum, no cutoff; r_list^2 = inf).
 // Per 64-block chunk the near blocks are listed in the wave's LDS scratch wblk (ascending);
 // their candidates are tested without branches, the outcomes kept as bits (BLK / P per block,
-// 32 blocks per batch), and each lane then writes the entries it keeps.  Itself and excluded
-// partners (all within 32 atoms of it) are dropped in the tests, only for blocks near the
-// wave's own atoms; atoms past n are staged far away, so the distance test drops them.  UNR
-// blocks are read at a time (more registers, fewer exposed LDS latencies); the plain path's
-// pair kernel uses 1 to keep its occupancy.
+// 32 blocks per batch), and each lane then appends the entries it keeps, four per pass.
+// Itself and excluded partners within 32 atoms of it are dropped in the tests, only for
+// blocks near the wave's own atoms; farther excluded partners are merged out entry by entry
+// (only while some lane of the wave still has one ahead); atoms past n are staged far away,
+// so the distance test drops them.  UNR blocks are read at a time (more registers, fewer
+// exposed LDS latencies); the plain path's pair kernel uses 1 to keep its occupancy.
 template <int UNR, bool PAD>
 __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool valid, const GPR_LDS gv_f4 *xs,
                                        const GPR_LDS gv_f4 *sph, GPR_LDS int *wblk, bool allpairs)
@@ -260,19 +261,13 @@ __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool v
     const int n = S.n;
     const size_t stride = (size_t)S.np * P;
     const gv_f4 pi = xs[valid ? i : n];
-    // bounding sphere of the wave's valid atoms
+    // bounding box of the wave's valid atoms
     const float big = 3.0e38f;
     const float mnx = wave16_min(valid ? pi.x : big), mxx = wave16_max(valid ? pi.x : -big);
     if (!(mnx <= mxx)) return 0;                                // no valid lane in this wave
     const float mny = wave16_min(valid ? pi.y : big), mxy = wave16_max(valid ? pi.y : -big);
     const float mnz = wave16_min(valid ? pi.z : big), mxz = wave16_max(valid ? pi.z : -big);
-    const float cx = 0.5f * (mnx + mxx), cy = 0.5f * (mny + mxy), cz = 0.5f * (mnz + mxz);
-    float d2 = 0.f;
-    if (valid) {
-        const float dx = pi.x - cx, dy = pi.y - cy, dz = pi.z - cz;
-        d2 = dx * dx + dy * dy + dz * dz;
-    }
-    const float rw = S.rl + sqrtf(wave16_max(d2)) * 1.0001f + 1e-6f;
+    const float rlb = S.rl;
     // finite even without a cutoff, so that the far-away atoms past n never pass
     const float rl2 = fminf(S.rl2, 1.0e30f);
     // atoms [iw, iw + 16) of the wave (lane 0 holds the first)
@@ -291,45 +286,64 @@ __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool v
     const int nblk = (n + BLK - 1) / BLK;
     constexpr int CPB = BLK / P;                                // candidates per block and lane
     constexpr int BATCH = 64 / CPB;                             // blocks per batch of bits
+    static_assert(CPB == 2, "a half batch is 32 candidates of 16 blocks");
     static_assert(BATCH % UNR == 0, "a batch holds whole groups of UNR blocks");
-    unsigned long long word = 0ull, bits = 0ull;
+    unsigned long long bits = 0ull;
+    // entries so far; the cnt % 4 entries of the unfinished group sit in the low 16-bit words
+    // of pend, in order; group g = cnt / 4 goes to Lw = L + g * stride, if g < Kg
+    unsigned long long pend = 0ull;
     int cnt = 0;
-    GPR_GLOBAL unsigned long long *Lw = L;                      // where the next full group goes
-    // entries kept in bits, whose blocks are wblk[base ...]; entry cnt is 16-bit word cnt % 4 of
-    // group cnt / 4: each entry is shifted in at the top of the group word, so that after four
-    // they sit in order from its low end, and the group is stored once complete
+    GPR_GLOBAL unsigned long long *Lw = L;
     auto emit = [&](int base) {
         __builtin_amdgcn_wave_barrier();
-        // two halves of 16 blocks (32 bits) each, entries in ascending order
+        const bool merge = __ballot(flo < fhi) != 0ull;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             unsigned b32 = h ? (unsigned)(bits >> 32) : (unsigned)bits;
             const int hb = base + 16 * h;
-            while (b32) {
-                int k[UNR], bk[UNR];
-                bool has[UNR];
+            if (!merge) {
+                // candidate k of the half is partner wblk[hb + k / 2] * BLK + (k % 2) * P + q:
+                // lane k < 32 holds that base, which the lanes read through the crossbar.  The
+                // passes are wave-uniform (a lane out of entries takes none), so that every lane
+                // is active at the crossbar read: an inactive source lane would read as zero.
+                const int jt = lane < 32 ? wblk[hb + (lane >> 1)] * BLK + (lane & 1) * P : 0;
+                while (__ballot(b32 != 0u) != 0ull) {
+                    const int c = min(4, __popc(b32));
+                    unsigned jv[4];
 #pragma unroll
-                for (int e = 0; e < UNR; ++e) {
-                    has[e] = b32 != 0u;
-                    k[e] = __builtin_ctz(b32 | (has[e] ? 0u : 1u));
-                    b32 &= b32 - 1u;
+                    for (int e = 0; e < 4; ++e) {
+                        const int k = __ffs(b32) - 1;           // -1 once no bit is left
+                        b32 &= b32 - 1u;
+                        const int j = __shfl(jt, k & 31, 64) + q;
+                        jv[e] = k >= 0 ? (unsigned)j : 0u;
+                    }
+                    const unsigned long long ch = (unsigned long long)(jv[0] | (jv[1] << 16)) |
+                                                  ((unsigned long long)(jv[2] | (jv[3] << 16)) << 32);
+                    const int sh = 16 * (cnt & 3);
+                    const unsigned long long lo = pend | (ch << sh);
+                    if ((cnt & 3) + c >= 4) {
+                        if (cnt < cap) gst(Lw, lo);
+                        Lw += stride;
+                        pend = sh ? ch >> (64 - sh) : 0ull;
+                    } else {
+                        pend = lo;
+                    }
+                    cnt += c;
                 }
-#pragma unroll
-                for (int e = 0; e < UNR; ++e) bk[e] = wblk[hb + k[e] / CPB];
-#pragma unroll
-                for (int e = 0; e < UNR; ++e) {
-                    if (!has[e]) continue;
-                    const unsigned j = (unsigned)(bk[e] * BLK + q + (k[e] % CPB) * P);
+            } else {
+                while (b32) {
+                    const int k = __ffs(b32) - 1;
+                    b32 &= b32 - 1u;
+                    const unsigned j = (unsigned)(wblk[hb + k / CPB] * BLK + q + (k % CPB) * P);
                     if (flo < fhi) {
                         while (flo < fhi && (unsigned)fj[flo] < j) ++flo;
                         if (flo < fhi && (unsigned)fj[flo] == j) continue;
                     }
-                    if (cnt < cap) {
-                        word = (word >> 16) | ((unsigned long long)j << 48);
-                        if ((cnt & 3) == 3) {
-                            gst(Lw, word);
-                            Lw += stride;
-                        }
+                    pend |= (unsigned long long)j << (16 * (cnt & 3));
+                    if ((cnt & 3) == 3) {
+                        if (cnt < cap) gst(Lw, pend);
+                        Lw += stride;
+                        pend = 0ull;
                     }
                     ++cnt;
                 }
@@ -342,9 +356,12 @@ __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool v
         const int b = cb + lane;
         bool near = b < nblk;
         if (near && !allpairs) {
+            // distance from the block's centre to the wave's box, against r_list + its radius
             const gv_f4 c = sph[b];
-            const float dx = c.x - cx, dy = c.y - cy, dz = c.z - cz;
-            const float lim = rw + c.w;
+            const float dx = fmaxf(0.f, fmaxf(mnx - c.x, c.x - mxx));
+            const float dy = fmaxf(0.f, fmaxf(mny - c.y, c.y - mxy));
+            const float dz = fmaxf(0.f, fmaxf(mnz - c.z, c.z - mxz));
+            const float lim = (rlb + c.w) * 1.0001f + 1e-6f;
             near = dx * dx + dy * dy + dz * dz < lim * lim;
         }
         const unsigned long long m = __ballot(near);
@@ -413,8 +430,8 @@ __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool v
     if (!valid) return 0;
     const int ng = min((cnt + 3) >> 2, S.Kg);
     if ((cnt & 3) != 0 && cnt < cap) {
-        for (int k = cnt & 3; k < 4; ++k) word = (word >> 16) | ((unsigned long long)(unsigned)n << 48);
-        gst(Lw, word);
+        const unsigned long long pad = (unsigned long long)n * 0x0001000100010001ull;
+        gst(Lw, pend | (pad << (16 * (cnt & 3))));
     }
     // PAD: the four sub-lists of an atom padded to the same number of groups with the
     // far-away atom n (exact zeros), so that one count (the largest, returned) serves the
