@@ -225,6 +225,9 @@ __device__ void block_spheres(const Dev &S, const float4 *xs, float4 *sph, int t
     }
 }
 
+// a value that every lane holds alike, as a scalar
+__device__ __forceinline__ float uniform_f(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+
 // min / max over the 16 atoms of a wave (the four lanes of an atom hold the same value)
 __device__ __forceinline__ float wave16_min(float v)
 {
@@ -263,10 +266,11 @@ __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool v
     const gv_f4 pi = xs[valid ? i : n];
     // bounding box of the wave's valid atoms
     const float big = 3.0e38f;
-    const float mnx = wave16_min(valid ? pi.x : big), mxx = wave16_max(valid ? pi.x : -big);
+    // (the same in every lane: held as scalars)
+    const float mnx = uniform_f(wave16_min(valid ? pi.x : big)), mxx = uniform_f(wave16_max(valid ? pi.x : -big));
     if (!(mnx <= mxx)) return 0;                                // no valid lane in this wave
-    const float mny = wave16_min(valid ? pi.y : big), mxy = wave16_max(valid ? pi.y : -big);
-    const float mnz = wave16_min(valid ? pi.z : big), mxz = wave16_max(valid ? pi.z : -big);
+    const float mny = uniform_f(wave16_min(valid ? pi.y : big)), mxy = uniform_f(wave16_max(valid ? pi.y : -big));
+    const float mnz = uniform_f(wave16_min(valid ? pi.z : big)), mxz = uniform_f(wave16_max(valid ? pi.z : -big));
     const float rlb = S.rl;
     // finite even without a cutoff, so that the far-away atoms past n never pass
     const float rl2 = fminf(S.rl2, 1.0e30f);
@@ -280,8 +284,10 @@ __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool v
     const GPR_GLOBAL int *fj = gconst(S.far_j);
     if (S.has_far && valid) { flo = gconst(S.far_start)[i]; fhi = gconst(S.far_start)[i + 1]; }
     const int cap = 4 * S.Kg;
-    GPR_GLOBAL unsigned long long *L =
-        (GPR_GLOBAL unsigned long long *)gmut(S.nbl) + (size_t)r * S.Kg * stride + (size_t)(valid ? i : 0) * P + q;
+    // the replica's lists (a scalar base) and this lane's column in them: group g of sub-list
+    // (i, q) is word g * np * P + i * P + q
+    GPR_GLOBAL unsigned long long *const Lr = (GPR_GLOBAL unsigned long long *)gmut(S.nbl) + (size_t)r * S.Kg * stride;
+    const unsigned col = (unsigned)((valid ? i : 0) * P + q), stride32 = (unsigned)stride;
     const int lane = threadIdx.x & 63;
     const int nblk = (n + BLK - 1) / BLK;
     constexpr int CPB = BLK / P;                                // candidates per block and lane
@@ -290,10 +296,9 @@ __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool v
     static_assert(BATCH % UNR == 0, "a batch holds whole groups of UNR blocks");
     unsigned long long bits = 0ull;
     // entries so far; the cnt % 4 entries of the unfinished group sit in the low 16-bit words
-    // of pend, in order; group g = cnt / 4 goes to Lw = L + g * stride, if g < Kg
+    // of pend, in order; group g = cnt / 4 goes to word g * stride + col, if g < Kg
     unsigned long long pend = 0ull;
     int cnt = 0;
-    GPR_GLOBAL unsigned long long *Lw = L;
     auto emit = [&](int base) {
         __builtin_amdgcn_wave_barrier();
         const bool merge = __ballot(flo < fhi) != 0ull;
@@ -322,8 +327,7 @@ __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool v
                     const int sh = 16 * (cnt & 3);
                     const unsigned long long lo = pend | (ch << sh);
                     if ((cnt & 3) + c >= 4) {
-                        if (cnt < cap) gst(Lw, lo);
-                        Lw += stride;
+                        if (cnt < cap) gst(Lr + ((unsigned)(cnt >> 2) * stride32 + col), lo);
                         pend = sh ? ch >> (64 - sh) : 0ull;
                     } else {
                         pend = lo;
@@ -341,8 +345,7 @@ __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool v
                     }
                     pend |= (unsigned long long)j << (16 * (cnt & 3));
                     if ((cnt & 3) == 3) {
-                        if (cnt < cap) gst(Lw, pend);
-                        Lw += stride;
+                        if (cnt < cap) gst(Lr + ((unsigned)(cnt >> 2) * stride32 + col), pend);
                         pend = 0ull;
                     }
                     ++cnt;
@@ -431,7 +434,7 @@ __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool v
     const int ng = min((cnt + 3) >> 2, S.Kg);
     if ((cnt & 3) != 0 && cnt < cap) {
         const unsigned long long pad = (unsigned long long)n * 0x0001000100010001ull;
-        gst(Lw, pend | (pad << (16 * (cnt & 3))));
+        gst(Lr + ((unsigned)(cnt >> 2) * stride32 + col), pend | (pad << (16 * (cnt & 3))));
     }
     // PAD: the four sub-lists of an atom padded to the same number of groups with the
     // far-away atom n (exact zeros), so that one count (the largest, returned) serves the
@@ -441,7 +444,7 @@ __device__ __noinline__ int build_wave(const Dev &S, int r, int i, int q, bool v
         kq = max(ng, __shfl_xor(ng, 1, 64));
         kq = max(kq, __shfl_xor(kq, 2, 64));
         const unsigned long long pad = (unsigned long long)n * 0x0001000100010001ull;
-        for (int w = ng; w < kq; ++w) gst(L + (size_t)w * stride, pad);
+        for (int w = ng; w < kq; ++w) gst(Lr + ((unsigned)w * stride32 + col), pad);
     }
     gmut(S.nbc)[(size_t)r * stride + (size_t)i * P + q] = (unsigned short)ng;
     if (cnt > cap) atomicOr(&S.err[ERR_LIST], 1);
