@@ -59,7 +59,7 @@ def test_fixed_dephasing_invariants_with_restarts(path, seed):
 @pytest.mark.slow
 def test_gpu_original_parrep_matches_direct_simulation():
     gpr = _gpr()
-    n = 400
+    n = 500
     g = original_parrep_exits(gpr.System(G.toy2d(seed=333), path=gpr.PATH_PERSISTENT), n, t_corr=100, t_phase=100)
     d = direct_exits(oracle.System(G.toy2d(seed=111)), n)
     gg = np.array([x[0] for x in g], float)

@@ -280,7 +280,7 @@ def test_dephase_branching_matches_oracle(path, seed):
 def test_toy_gen_parrep_gpu_matches_direct_simulation():
     from helpers import direct_exits, gen_parrep_exits
     gpr = _gpr()
-    n = 400
+    n = 500
     say("toy Gen.ParRep on GPU")
     g = gen_parrep_exits(gpr.System(G.toy2d(seed=303), path=gpr.PATH_PERSISTENT), n, t_corr=100)
     d = direct_exits(oracle.System(G.toy2d(seed=101)), n)
